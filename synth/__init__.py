@@ -1,0 +1,18 @@
+"""Seeded synthetic microscopy-like inputs shared by the tests, the benchmark
+and the smoke check.
+
+This module holds none of the deconvolution arithmetic: it renders objects
+(points, Gaussian blobs, tubular filaments), samples Gaussian PSFs and draws
+photon and read noise.  Blurring an object is left to the caller (the oracle
+in tests, the library in the benchmark), which passes the blurred image to
+`add_noise`.
+
+Shapes are (z, y, x), C order, x contiguous.  The paper's own test images are
+not used: these inputs stand in for them with the shapes, value ranges and
+structure described in the design doc.
+"""
+from .volumes import (CONFIGS, SWEEP_PSFS, VolumeConfig, add_noise, batched_configs,
+                      flat_start, gaussian_factors, gaussian_psf, make_objects, psf_for)
+
+__all__ = ["CONFIGS", "SWEEP_PSFS", "VolumeConfig", "add_noise", "batched_configs", "flat_start",
+           "gaussian_factors", "gaussian_psf", "make_objects", "psf_for"]

@@ -1,0 +1,315 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by
+mathematics, never against the oracle itself.  CPU only.
+
+Each test names the passage or identity it checks.  Integer-valued inputs
+make the sums exact in double precision, so those comparisons are exact."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.conftest import read_golden
+
+RNG = np.random.default_rng(12345)
+
+
+def _int_array(shape, lo=-4, hi=5, rng=RNG):
+    return rng.integers(lo, hi, size=shape).astype(np.float64)
+
+
+TINY_SHAPES = [
+    # (m, p): n = 1..4, p_i = 0, m_i = 1 and 2p_i >= m_i all occur.
+    ((5,), (2,)),
+    ((1,), (3,)),
+    ((3, 4), (1, 2)),
+    ((2, 3), (3, 1)),
+    ((4, 1), (0, 2)),
+    ((3, 4, 5), (1, 2, 1)),
+    ((2, 2, 3), (0, 1, 2)),
+    ((1, 3, 2), (2, 0, 1)),
+    ((2, 1, 3, 2), (1, 0, 2, 1)),
+]
+
+
+# ---------------------------------------------------------------- Property 1
+def test_eq1_golden_2d(golden):
+    """Eq. 1 written out by hand (block Toeplitz of (S1) bands) equals both
+    the recursive builder and the convolution applied to unit vectors."""
+    g = golden("eq1_block_toeplitz_2d.txt")
+    A_ref = np.array([[float(v) for v in r.split()] for r in g["main"]])
+    H = np.array([[2, 3, 5], [7, 11, 13], [17, 19, 23]], dtype=np.float64)
+    A = oracle.explicit_A((2, 2), H)
+    assert A.shape == (16, 4)
+    np.testing.assert_array_equal(A, A_ref)
+    for c in range(4):
+        e = np.zeros(4)
+        e[c] = 1.0
+        np.testing.assert_array_equal(oracle.conv_full(e.reshape(2, 2), H).ravel(), A_ref[:, c])
+
+
+def test_s1_s8_golden_1d(golden):
+    """(S1) and its transpose (S8) for n = 1."""
+    g = golden("s1_s8_banded_1d.txt")
+    S1 = np.array([[float(v) for v in r.split()] for r in g["S1"]])
+    S8 = np.array([[float(v) for v in r.split()] for r in g["S8"]])
+    h = np.array([2.0, 3.0, 5.0])
+    np.testing.assert_array_equal(oracle.explicit_A((4,), h), S1)
+    np.testing.assert_array_equal(S1.T, S8)
+    y = np.array([1.0, -2.0, 3.0, 4.0, -5.0, 6.0])
+    np.testing.assert_array_equal(oracle.conv_adjoint(y, h), S8 @ y)
+
+
+@pytest.mark.parametrize("m,p", TINY_SHAPES)
+def test_O1_full_conv_equals_explicit_A(m, p):
+    """Y^v = A_n^h X^v (Eq. 1) with A from the block recursion, exact."""
+    h = _int_array([2 * q + 1 for q in p])
+    x = _int_array(m)
+    y = oracle.conv_full(x, h)
+    assert y.shape == tuple(a + 2 * b for a, b in zip(m, p))
+    A = oracle.explicit_A(m, h)
+    np.testing.assert_array_equal(A @ x.ravel(), y.ravel())
+
+
+@pytest.mark.parametrize("m,p", TINY_SHAPES)
+def test_O2_adjoint_is_transpose(m, p):
+    """(A_n^h)^T applied to Y (Property 2's left side), exact on integers,
+    plus <Ax, y> = <x, A^T y> on random reals.  H is asymmetric so a
+    missing flip cannot pass."""
+    h = _int_array([2 * q + 1 for q in p])
+    r = _int_array([a + 2 * b for a, b in zip(m, p)])
+    A = oracle.explicit_A(m, h)
+    g = oracle.conv_adjoint(r, h)
+    assert g.shape == tuple(m)
+    np.testing.assert_array_equal(A.T @ r.ravel(), g.ravel())
+    xr = RNG.standard_normal(m)
+    yr = RNG.standard_normal(r.shape)
+    hr = RNG.standard_normal(h.shape)
+    lhs = float(np.sum(oracle.conv_full(xr, hr) * yr))
+    rhs = float(np.sum(xr * oracle.conv_adjoint(yr, hr)))
+    assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+
+
+@pytest.mark.parametrize("m,p", TINY_SHAPES)
+def test_O3_property2_literal_crop(m, p):
+    """Eq. 2 literally (convolve with H~, extent m+4p, crop at 2p) equals the
+    transpose; the uncropped result equals the extended transpose (S9),
+    i.e. the full-convolution matrix of H~ applied to Y."""
+    h = _int_array([2 * q + 1 for q in p])
+    r = _int_array([a + 2 * b for a, b in zip(m, p)])
+    g_lit, ext = oracle.conv_adjoint_literal(r, h, return_extended=True)
+    assert ext.shape == tuple(a + 4 * b for a, b in zip(m, p))
+    np.testing.assert_array_equal(g_lit, oracle.conv_adjoint(r, h))
+    hf = h[tuple(slice(None, None, -1) for _ in h.shape)]
+    A_ext = oracle.explicit_A(r.shape, hf)
+    np.testing.assert_array_equal(A_ext @ r.ravel(), ext.ravel())
+
+
+# ---------------------------------------------------------------- library special cases
+@pytest.mark.parametrize("m,p", [((7, 9), (2, 3)), ((5, 6, 4), (1, 2, 1)), ((3, 3, 3), (2, 2, 2))])
+def test_O4_scipy_direct(m, p):
+    from scipy import signal
+    h = RNG.standard_normal([2 * q + 1 for q in p])
+    x = RNG.standard_normal(m)
+    y = oracle.conv_full(x, h)
+    np.testing.assert_allclose(y, signal.convolve(x, h, mode="full", method="direct"), rtol=0, atol=1e-12)
+    r = RNG.standard_normal(y.shape)
+    np.testing.assert_allclose(oracle.conv_adjoint(r, h), signal.correlate(r, h, mode="valid", method="direct"),
+                               rtol=0, atol=1e-12)
+
+
+def test_O12_fft_crosscheck_medium():
+    """A larger 3-D case against an FFT (test-only), ~1e-12."""
+    m, p = (12, 20, 24), (3, 4, 5)
+    h = RNG.standard_normal([2 * q + 1 for q in p])
+    x = RNG.standard_normal(m)
+    y = oracle.conv_full(x, h)
+    shp = y.shape
+    ax = (0, 1, 2)
+    yf = np.fft.irfftn(np.fft.rfftn(x, shp, axes=ax) * np.fft.rfftn(h, shp, axes=ax), shp, axes=ax)
+    assert np.max(np.abs(y - yf)) <= 1e-11 * np.max(np.abs(y))
+    r = RNG.standard_normal(shp)
+    # correlation: G[k] = sum_j h[j] r[k+j] = (r conv flip(h))[k+2p]
+    hf = h[::-1, ::-1, ::-1]
+    big = [a + 2 * b for a, b in zip(shp, h.shape)]
+    full = np.fft.irfftn(np.fft.rfftn(r, big, axes=ax) * np.fft.rfftn(hf, big, axes=ax), big, axes=ax)
+    sl = tuple(slice(2 * q, 2 * q + a) for q, a in zip(p, m))
+    g = oracle.conv_adjoint(r, h)
+    assert np.max(np.abs(g - full[sl])) <= 1e-11 * np.max(np.abs(g))
+
+
+# ---------------------------------------------------------------- closed forms
+def test_O5_delta_psf():
+    x = _int_array((4, 5, 6))
+    p = (1, 2, 3)
+    h = np.zeros([2 * q + 1 for q in p])
+    h[p] = 1.0  # delta at the centre
+    y = oracle.conv_full(x, h)
+    np.testing.assert_array_equal(y, np.pad(x, [(q, q) for q in p]))
+    r = _int_array(y.shape)
+    np.testing.assert_array_equal(oracle.conv_adjoint(r, h), r[1:5, 2:7, 3:9])
+    h0 = np.zeros_like(h)
+    h0[0, 0, 0] = 1.0  # delta at index 0: Y[:m] = X, rest zero
+    y0 = oracle.conv_full(x, h0)
+    np.testing.assert_array_equal(y0[:4, :5, :6], x)
+    assert np.count_nonzero(y0) == np.count_nonzero(x)
+
+
+def test_O6_binomial_rows(golden):
+    rows = golden("binomial_rows.txt")["rows"]
+    for line in rows:
+        _, xa, hb, want = [s.split() for s in line.split("|")]
+        x = np.array([float(v) for v in xa])
+        h = np.array([float(v) for v in hb])
+        w = np.array([float(v) for v in want])
+        np.testing.assert_array_equal(oracle.conv_full(x, h), w)
+    # separable n-D products of binomials stay products of binomials
+    c2, c4 = np.array([1.0, 2, 1]), np.array([1.0, 4, 6, 4, 1])
+    c6 = np.array([1.0, 6, 15, 20, 15, 6, 1])
+    x = np.einsum("i,j,k->ijk", c4, c2, c4)
+    h = np.einsum("i,j,k->ijk", c2, c4, c2)
+    np.testing.assert_array_equal(oracle.conv_full(x, h), np.einsum("i,j,k->ijk", c6, c6, c6))
+
+
+def test_O7_mass_and_moments_add():
+    x = RNG.random((6, 7, 8))
+    h = RNG.random((3, 5, 7))
+    y = oracle.conv_full(x, h)
+    assert abs(y.sum() - x.sum() * h.sum()) <= 1e-12 * y.sum()
+    for ax in range(3):
+        def mom(a):
+            other = tuple(i for i in range(3) if i != ax)
+            w = a.sum(axis=other)
+            t = np.arange(w.size, dtype=np.float64)
+            mu = (w * t).sum() / w.sum()
+            return mu, (w * (t - mu) ** 2).sum() / w.sum()
+        mx, vx = mom(x)
+        mh, vh = mom(h)
+        my, vy = mom(y)
+        assert abs(my - (mx + mh)) <= 1e-12 * my
+        assert abs(vy - (vx + vh)) <= 1e-11 * vy
+
+
+def test_O8_separable_equals_nd():
+    fz, fy, fx = RNG.random(5), RNG.random(3), RNG.random(7)
+    h = np.einsum("i,j,k->ijk", fz, fy, fx)
+    x = RNG.standard_normal((6, 5, 9))
+    a = oracle.conv_full(x, h)
+    b = oracle.conv_full_separable(x, [fz, fy, fx])
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
+# ---------------------------------------------------------------- sampled evaluation
+def test_at_functions_match_dense():
+    x = RNG.standard_normal((5, 6, 7))
+    h = RNG.standard_normal((3, 5, 3))
+    y = oracle.conv_full(x, h)
+    idx = RNG.choice(y.size, 50, replace=False)
+    np.testing.assert_array_equal(oracle.conv_full_at(x, h, idx), y.ravel()[idx])
+    g = oracle.conv_adjoint(y, h)
+    idx = RNG.choice(g.size, 40, replace=False)
+    np.testing.assert_array_equal(oracle.conv_adjoint_at(y, h, idx), g.ravel()[idx])
+
+
+# ---------------------------------------------------------------- gradient in H
+def test_O13_dH_is_transpose_of_conv_in_H():
+    """Convolution commutes: Y = A_X vec(H), so the H-gradient is A_X^T R.
+    X has odd extents so it can serve as the template of explicit_A."""
+    x = _int_array((3, 5))
+    h = _int_array((5, 3))
+    r = _int_array((3 + 4, 5 + 2))
+    dh = oracle.conv_dH(x, r, h.shape)
+    A_x = oracle.explicit_A(h.shape, x)  # acts on vec(H)
+    np.testing.assert_array_equal(A_x @ h.ravel(), oracle.conv_full(x, h).ravel())
+    np.testing.assert_array_equal(A_x.T @ r.ravel(), dh.ravel())
+
+
+def test_O13_dH_central_differences():
+    """The loss is quadratic in H, so a central difference is exact up to
+    rounding."""
+    x = RNG.random((4, 5, 6))
+    h = RNG.random((3, 3, 5))
+    y = RNG.random((6, 7, 10))
+    r = oracle.conv_full(x, h) - y
+    dh = oracle.conv_dH(x, r, h.shape)
+    eps = 1e-3
+    for j in [(0, 0, 0), (1, 2, 3), (2, 1, 4), (0, 2, 2)]:
+        hp, hm = h.copy(), h.copy()
+        hp[j] += eps
+        hm[j] -= eps
+        lp = 0.5 * np.sum((oracle.conv_full(x, hp) - y) ** 2)
+        lm = 0.5 * np.sum((oracle.conv_full(x, hm) - y) ** 2)
+        assert abs((lp - lm) / (2 * eps) - dh[j]) <= 1e-8 * max(1.0, abs(dh[j]))
+
+
+# ---------------------------------------------------------------- the iteration
+def test_O9_eq6_literal_equals_fused():
+    x_true = RNG.random((6, 7))
+    h = RNG.random((3, 5))
+    y = oracle.conv_full(x_true, h) + 0.01 * RNG.standard_normal((8, 11))
+    x0 = np.full(x_true.shape, 0.5)
+    xa, sa, da, _ = oracle.deconv(y, h, x0, 20)
+    xb, sb, db, _ = oracle.deconv(y, h, x0, 20, literal_eq6=True)
+    assert da == db == 20
+    np.testing.assert_allclose(xa, xb, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(sa[:, 0], sb[:, 0], rtol=1e-12)
+
+
+def test_O10_converges_to_nnls_and_kkt():
+    from scipy.optimize import nnls
+    m, hs = (4, 5), (3, 3)
+    h = RNG.random(hs) + 0.1
+    x_true = np.maximum(RNG.standard_normal(m), 0)
+    y = oracle.conv_full(x_true, h) + 0.05 * RNG.standard_normal((6, 7))
+    x, stats, done, status = oracle.deconv(y, h, np.zeros(m), 4000)
+    assert status in (0, 1)
+    assert np.all(x >= 0)
+    f = stats[:, 0]
+    assert np.all(np.diff(f[: done + 1]) < 0)  # strict decrease on every accepted step
+    A = oracle.explicit_A(m, h)
+    x_ref, _ = nnls(A, y.ravel())
+    assert np.linalg.norm(x.ravel() - x_ref) <= 1e-6 * max(1.0, np.linalg.norm(x_ref))
+    g = A.T @ (A @ x.ravel() - y.ravel())
+    act = x.ravel() <= 1e-12
+    assert np.all(g[act] >= -1e-6)
+    assert np.all(np.abs(g[~act]) <= 1e-6)
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.5])
+def test_O11_delta_psf_one_step(lam):
+    """Delta PSF: A^T A = I, delta_0 = 1/(1+lam), X^0 = 0, so one step gives
+    max(crop_p(Y)/(1+lam), 0) exactly."""
+    p = (1, 2)
+    h = np.zeros((3, 5))
+    h[p] = 1.0
+    y = _int_array((5, 8))
+    x, stats, done, _ = oracle.deconv(y, h, np.zeros((3, 4)), 1, lam=lam)
+    assert done == 1
+    np.testing.assert_array_equal(x, np.maximum(y[1:4, 2:6] / (1.0 + lam), 0))
+    assert stats[1, 1] == 1.0 / (1.0 + lam)
+
+
+def test_deconv_stops_at_stationary_point():
+    """Y = A X^0 exactly gives f(X^0) = 0: no strict decrease is possible."""
+    h = _int_array((3, 3), 1, 4)
+    x0 = _int_array((4, 4), 0, 3)
+    y = oracle.conv_full(x0, h)
+    x, stats, done, status = oracle.deconv(y, h, x0, 5)
+    assert done == 0 and status == 1
+    np.testing.assert_array_equal(x, x0)
+
+
+def test_deconv_nonfinite_stops():
+    h = np.ones((3, 3)) / 9
+    y = np.ones((6, 6))
+    y[2, 2] = np.nan
+    _, _, done, status = oracle.deconv(y, h, np.zeros((4, 4)), 3)
+    assert done == 0 and status == 2
+
+
+def test_deconv_replay_matches_search():
+    x_true = RNG.random((5, 6))
+    h = RNG.random((3, 3))
+    y = oracle.conv_full(x_true, h)
+    x0 = np.full((5, 6), 0.3)
+    xa, sa, da, _ = oracle.deconv(y, h, x0, 10)
+    xb, sb, db, _ = oracle.deconv(y, h, x0, 10, deltas=sa[1:, 1])
+    np.testing.assert_array_equal(xa, xb)
