@@ -1,0 +1,129 @@
+/*
+ * ndconv.h -- C ABI of the gfx950 (MI355X) library for the n-dimensional
+ * full convolution, its transpose, and the projected-gradient deconvolution
+ * built from them, following "Properties on n-dimensional convolution for
+ * image deconvolution" (arXiv 1711.11224).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  n          number of axes, 1 <= n <= 3 (an n-D problem with n < 3 is run
+ *             as 3-D with unit extents and zero half-widths in front).
+ *  m[0..n)    extent of X on each axis, m_i >= 1 (the X size of Eq. 4).
+ *  p[0..n)    PSF half-widths, p_i >= 0; H has extent 2p_i+1 (Property 1's
+ *             template domain {0..2p_i}).  2p_i >= m_i is allowed.
+ *  Y extent   m_i + 2p_i (Eq. 4).
+ *  Layout     every array is dense C order, axis 0 slowest, matching the
+ *             row partitioning of the vectorisation {.}^v under Eq. 1.
+ *  Pointers   every array pointer is a DEVICE pointer on the current HIP
+ *             device, owned by the caller; the library never keeps it after
+ *             the call returns and never allocates memory the caller sees.
+ *  dtype      NDC_F32 (float) or NDC_F64 (double): the storage type of X, H,
+ *             Y and of any workspace arrays.
+ *  precision  NDC_PREC_NATIVE computes the multiply-adds in the storage type.
+ *             NDC_PREC_BF16 rounds both operands to bfloat16 (round to nearest
+ *             even) and accumulates in float; NDC_PREC_SPLIT_BF16 writes each
+ *             operand as hi + lo with hi = bf16(v), lo = bf16(v - hi) and sums
+ *             hi*hi + hi*lo + lo*hi in float.  The bf16 forms need NDC_F32.
+ *  stream     a hipStream_t passed as void*; NULL is the null stream.  All
+ *             work is enqueued asynchronously on it.
+ *
+ * Errors: every argument check runs before anything is enqueued.  On a
+ * negative status nothing was launched and no output was written.
+ * NDC_EDEVICE reports a failed launch.  No entry point throws or aborts.
+ * Calls on different streams that share an output buffer race.
+ */
+#ifndef NDCONV_H
+#define NDCONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define NDC_API __attribute__((visibility("default")))
+#else
+#define NDC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NDC_OK = 0,
+  NDC_EINVAL = -1,       /* bad n, extent, half-width, count, pointer or scalar */
+  NDC_EUNSUPPORTED = -2, /* valid request this build does not implement      */
+  NDC_EALIAS = -3,       /* an output overlaps an input or another output     */
+  NDC_ENONFINITE = -4,   /* reported in deconvolution status words only       */
+  NDC_EDEVICE = -5,      /* a HIP runtime call or kernel launch failed         */
+  NDC_EWORKSPACE = -6    /* workspace missing or smaller than required         */
+} ndc_status;
+
+typedef enum { NDC_F32 = 0, NDC_F64 = 1 } ndc_dtype;
+
+typedef enum {
+  NDC_PREC_NATIVE = 0,
+  NDC_PREC_BF16 = 1,
+  NDC_PREC_SPLIT_BF16 = 2
+} ndc_precision;
+
+/* Forward operator, Property 1 and Eq. 4: the full discrete convolution
+ *   Y[s] = sum_{j in prod [0,2p_i]} H[j] X[s-j],  s in prod [0, m_i+2p_i),
+ * with X taken as zero outside prod [0, m_i).  Y (prod(m_i+2p_i) elements)
+ * is fully overwritten; X and H (prod(m_i), prod(2p_i+1) elements) are read. */
+NDC_API int conv_full_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *H,
+                 void *Y, int dtype, int precision, void *stream);
+
+/* Transpose, Property 2 and Eq. 2: (A_n^h)^T applied to R equals the crop
+ * M_{2p} of R convolved with the flipped PSF H~(s) = H(2p-s), i.e.
+ *   X[k] = sum_{j in prod [0,2p_i]} H[j] R[k+j],  k in prod [0, m_i).
+ * R has extent m_i+2p_i; X (prod(m_i) elements) is fully overwritten. */
+NDC_API int conv_adjoint_nd(int n, const int64_t *m, const int64_t *p, const void *R, const void *H,
+                    void *X, int dtype, int precision, void *stream);
+
+/* Gradient of 1/2 ||X (x) H - Y||^2 with respect to H, given the residual
+ * G = X (x) H - Y (extent m_i+2p_i):  dH[j] = sum_k X[k] G[k+j],
+ * j in prod [0,2p_i].  Convolution commutes, so this is Property 1's
+ * transpose with X as the template.  dH (prod(2p_i+1)) is overwritten.
+ * ws must hold conv_dH_workspace_bytes() bytes (may be 0 -> ws may be NULL). */
+NDC_API size_t conv_dH_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype);
+NDC_API int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH,
+               int dtype, void *ws, size_t ws_bytes, void *stream);
+
+/* Projected-gradient deconvolution (Steps 1-3 of the paper's algorithm,
+ * gradient by Eq. 6 in its fused form A^T(AX - Y) + lambda X):
+ *   minimise f(X) = 1/2 ||A X - Y||^2 + lambda/2 ||X||^2  s.t. X >= 0,
+ *   X^{k+1} = max(X^k - delta_k grad f(X^k), 0).
+ * delta_k is accepted by the paper's rule f(X^{k+1}) < f(X^k): trials start
+ * at delta_0 = 1/(||H||_1^2 + lambda) and halve, at most 30 per step; f is
+ * evaluated in double precision.  lambda = 0 is the paper's objective.
+ *
+ *  Y      extent m_i+2p_i, read.   H extent 2p_i+1, read.
+ *  X      in: X^0 (caller's initial solution); out: X^{iters_done}.
+ *  iters  accepted steps to run (>= 0).
+ *  ws     workspace of at least deconv_workspace_bytes() bytes, caller-owned,
+ *         device memory; contents on entry are ignored.
+ *  stats  nullable device array of 4*(iters+1) doubles: row k holds
+ *         (f(X^k), delta used to reach X^k, rejected trials, ||X^k-X^{k-1}||);
+ *         row 0 holds f(X^0).  Rows past iters_done are left untouched.
+ *  info   nullable device array of 2 ints: (iters_done, status) with status
+ *         0 = all steps done, 1 = stopped, no decrease within 30 halvings,
+ *         NDC_ENONFINITE = stopped on a non-finite objective.
+ *
+ * The call waits on `stream` between batches of launched steps to learn how
+ * many steps were accepted (normally once per call); X, stats and info are
+ * complete when it returns NDC_OK. */
+NDC_API size_t deconv_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype, int precision);
+NDC_API int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
+                   int iters, double lambda, int dtype, int precision, void *ws, size_t ws_bytes,
+                   double *stats, int *info, void *stream);
+
+/* Static text for a status code (never NULL). */
+NDC_API const char *ndc_strerror(int status);
+
+/* Library ABI version: (major << 16) | minor. */
+NDC_API int ndc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NDCONV_H */

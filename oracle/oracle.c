@@ -65,7 +65,8 @@ static int64_t ora_flat(int n, const int64_t *v, const int64_t *e) {
 }
 
 /* y(s) = sum_k x(k) h(s-k), summed over the taps j = s-k that keep both
- * k inside [0,m) and j inside [0,2p] (zero extension outside). */
+ * k inside [0,m) and j inside [0,2p] (zero extension outside).  Taps are
+ * visited in lexicographic order; the last axis is the inner loop. */
 static double ora_full_one(int n, const int64_t *m, const int64_t *p,
                            const double *X, const double *H, const int64_t *s) {
   int64_t lo[ORA_MAXN], hi[ORA_MAXN], j[ORA_MAXN], eh[ORA_MAXN], k[ORA_MAXN];
@@ -76,11 +77,17 @@ static double ora_full_one(int n, const int64_t *m, const int64_t *p,
     if (lo[i] > hi[i]) return 0.0;
     j[i] = lo[i];
   }
+  const int L = n - 1;
   double acc = 0.0;
   for (;;) {
-    for (int i = 0; i < n; ++i) k[i] = s[i] - j[i];
-    acc += H[ora_flat(n, j, eh)] * X[ora_flat(n, k, m)];
-    int i = n - 1;
+    /* row of H at j[0..L-1], column 0; row of X at k[0..L-1] = s - j, column 0 */
+    j[L] = 0;
+    for (int i = 0; i < L; ++i) k[i] = s[i] - j[i];
+    k[L] = 0;
+    const double *hrow = H + ora_flat(n, j, eh);
+    const double *xrow = X + ora_flat(n, k, m);
+    for (int64_t t = lo[L]; t <= hi[L]; ++t) acc += hrow[t] * xrow[s[L] - t];
+    int i = L - 1;
     while (i >= 0) {
       if (++j[i] <= hi[i]) break;
       j[i] = lo[i];
@@ -91,7 +98,8 @@ static double ora_full_one(int n, const int64_t *m, const int64_t *p,
   return acc;
 }
 
-/* (A^T r)(k) = sum_{j in [0,2p]} h(j) r(k+j): every tap is in range. */
+/* (A^T r)(k) = sum_{j in [0,2p]} h(j) r(k+j): every tap is in range.  Taps
+ * in lexicographic order; the last axis is the inner loop. */
 static double ora_adj_one(int n, const int64_t *m, const int64_t *p,
                           const double *R, const double *H, const int64_t *k) {
   int64_t j[ORA_MAXN], eh[ORA_MAXN], er[ORA_MAXN], t[ORA_MAXN];
@@ -100,11 +108,16 @@ static double ora_adj_one(int n, const int64_t *m, const int64_t *p,
     er[i] = m[i] + 2 * p[i];
     j[i] = 0;
   }
+  const int L = n - 1;
   double acc = 0.0;
   for (;;) {
-    for (int i = 0; i < n; ++i) t[i] = k[i] + j[i];
-    acc += H[ora_flat(n, j, eh)] * R[ora_flat(n, t, er)];
-    int i = n - 1;
+    for (int i = 0; i < L; ++i) t[i] = k[i] + j[i];
+    t[L] = k[L];
+    j[L] = 0;
+    const double *hrow = H + ora_flat(n, j, eh);
+    const double *rrow = R + ora_flat(n, t, er);
+    for (int64_t c = 0; c <= 2 * p[L]; ++c) acc += hrow[c] * rrow[c];
+    int i = L - 1;
     while (i >= 0) {
       if (++j[i] <= 2 * p[i]) break;
       j[i] = 0;

@@ -1,0 +1,67 @@
+"""ctypes binding of libndconv.so: the C ABI of include/ndconv.h with the
+same names and argument order.  Marshalling only; every step of the
+computation runs in the library's HIP kernels.  Importing this module fails
+loudly when the library has not been built."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libndconv.so")
+
+NDC_OK, NDC_EINVAL, NDC_EUNSUPPORTED, NDC_EALIAS = 0, -1, -2, -3
+NDC_ENONFINITE, NDC_EDEVICE, NDC_EWORKSPACE = -4, -5, -6
+NDC_F32, NDC_F64 = 0, 1
+NDC_PREC_NATIVE, NDC_PREC_BF16, NDC_PREC_SPLIT_BF16 = 0, 1, 2
+
+EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_dH_nd",
+           "deconv_workspace_bytes", "deconv_iterate", "ndc_strerror", "ndc_version")
+
+
+class NdcError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (what or "ndconv", strerror(status), status))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libndconv.so is not built; run __graft_entry__.build() or "
+                          "python paper_1711_11224_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vp, c_int, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    lib.conv_full_nd.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, c_int, vp]
+    lib.conv_full_nd.restype = c_int
+    lib.conv_adjoint_nd.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, c_int, vp]
+    lib.conv_adjoint_nd.restype = c_int
+    lib.conv_dH_workspace_bytes.argtypes = [c_int, i64p, i64p, c_int]
+    lib.conv_dH_workspace_bytes.restype = sz
+    lib.conv_dH_nd.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, vp, sz, vp]
+    lib.conv_dH_nd.restype = c_int
+    lib.deconv_workspace_bytes.argtypes = [c_int, i64p, i64p, c_int, c_int]
+    lib.deconv_workspace_bytes.restype = sz
+    lib.deconv_iterate.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, ctypes.c_double, c_int, c_int,
+                                   vp, sz, vp, vp, vp]
+    lib.deconv_iterate.restype = c_int
+    lib.ndc_strerror.argtypes = [c_int]
+    lib.ndc_strerror.restype = ctypes.c_char_p
+    lib.ndc_version.argtypes = []
+    lib.ndc_version.restype = c_int
+    return lib
+
+
+lib = _load()
+
+
+def strerror(status: int) -> str:
+    return lib.ndc_strerror(int(status)).decode()
+
+
+def i64_array(vals):
+    arr = (ctypes.c_int64 * max(1, len(vals)))(*[int(v) for v in vals])
+    return arr
+
+
+def check(status, what):
+    if status != NDC_OK:
+        raise NdcError(status, what)

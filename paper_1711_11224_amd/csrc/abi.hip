@@ -1,0 +1,304 @@
+// C ABI entry points (include/ndconv.h): argument checks, n-D folding,
+// kernel-variant choice and launches.  Every check runs before anything is
+// enqueued; nothing here throws, aborts or allocates device memory.
+#include <limits.h>
+#include <math.h>
+#include <string.h>
+
+#include "ndc_device.h"
+#include "ndc_internal.h"
+
+namespace ndc {
+
+size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision);
+int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
+               double lambda, int dtype, int precision, void *ws, double *stats, int *info, hipStream_t s);
+bool mfma_supported(const Geom &g, int dtype, int precision);
+ConvPlan plan_conv_mfma(const Geom &g, int dtype, int precision);
+hipError_t launch_conv_mfma(const ConvPlan &pl, const Geom &g, int dtype, int precision, const void *in,
+                            const void *H, void *out, const Epi &ep, hipStream_t s);
+
+bool fold3(int n, const int64_t *m, const int64_t *p, int64_t m3[3], int64_t p3[3]) {
+  if (n < 1 || n > 3) return false;
+  for (int i = 0; i < 3; ++i) {
+    m3[i] = 1;
+    p3[i] = 0;
+  }
+  for (int i = 0; i < n; ++i) {
+    m3[3 - n + i] = m[i];
+    p3[3 - n + i] = p[i];
+  }
+  return true;
+}
+
+Geom forward_geom(const int64_t m3[3], const int64_t p3[3]) {
+  Geom g;
+  g.oz = (int)(m3[0] + 2 * p3[0]);
+  g.oy = (int)(m3[1] + 2 * p3[1]);
+  g.ox = (int)(m3[2] + 2 * p3[2]);
+  g.iz = (int)m3[0];
+  g.iy = (int)m3[1];
+  g.ix = (int)m3[2];
+  g.kz = (int)(2 * p3[0] + 1);
+  g.ky = (int)(2 * p3[1] + 1);
+  g.kx = (int)(2 * p3[2] + 1);
+  g.offz = (int)(2 * p3[0]);
+  g.offy = (int)(2 * p3[1]);
+  g.offx = (int)(2 * p3[2]);
+  g.flip = 1;
+  return g;
+}
+
+Geom adjoint_geom(const int64_t m3[3], const int64_t p3[3]) {
+  Geom g;
+  g.oz = (int)m3[0];
+  g.oy = (int)m3[1];
+  g.ox = (int)m3[2];
+  g.iz = (int)(m3[0] + 2 * p3[0]);
+  g.iy = (int)(m3[1] + 2 * p3[1]);
+  g.ix = (int)(m3[2] + 2 * p3[2]);
+  g.kz = (int)(2 * p3[0] + 1);
+  g.ky = (int)(2 * p3[1] + 1);
+  g.kx = (int)(2 * p3[2] + 1);
+  g.offz = g.offy = g.offx = 0;
+  g.flip = 0;
+  return g;
+}
+
+static int64_t grid_blocks(dim3 g) { return (int64_t)g.x * g.y * g.z; }
+
+ConvPlan plan_conv(const Geom &g, int dtype, int precision) {
+  if (mfma_supported(g, dtype, precision)) return plan_conv_mfma(g, dtype, precision);
+  ConvPlan pl;
+  pl.variant = 0;
+  pl.grid = valu_grid(g, 1);
+  pl.block = dim3(256);
+  pl.lds_bytes = 0;
+  pl.nblocks = grid_blocks(pl.grid);
+  return pl;
+}
+
+hipError_t launch_conv(const ConvPlan &pl, const Geom &g, int dtype, int precision, const void *in, const void *H,
+                       void *out, const Epi &ep, hipStream_t s) {
+  if (pl.variant == 1) return launch_conv_mfma(pl, g, dtype, precision, in, H, out, ep, s);
+  return launch_conv_valu(g, dtype, precision, in, H, out, ep, 1, g.kz, s);
+}
+
+}  // namespace ndc
+
+using namespace ndc;
+
+namespace {
+
+// Largest extent any axis may take (input, output or tap) so that every
+// in-kernel index fits in int; the 3-D folding keeps products in int64.
+constexpr int64_t kMaxAxis = (int64_t)1 << 24;
+constexpr int64_t kMaxElems = (int64_t)1 << 36;
+constexpr int kMaxGridYZ = 65535;
+
+int check_problem(int n, const int64_t *m, const int64_t *p, int dtype, int precision, int64_t m3[3],
+                  int64_t p3[3]) {
+  if (n < 1 || !m || !p) return NDC_EINVAL;
+  if (n > 3) return NDC_EUNSUPPORTED;
+  for (int i = 0; i < n; ++i)
+    if (m[i] < 1 || p[i] < 0) return NDC_EINVAL;
+  if (dtype != NDC_F32 && dtype != NDC_F64) return NDC_EINVAL;
+  if (precision != NDC_PREC_NATIVE && precision != NDC_PREC_BF16 && precision != NDC_PREC_SPLIT_BF16)
+    return NDC_EINVAL;
+  if (dtype == NDC_F64 && precision != NDC_PREC_NATIVE) return NDC_EUNSUPPORTED;
+  fold3(n, m, p, m3, p3);
+  int64_t ny = 1;
+  for (int i = 0; i < 3; ++i) {
+    if (m3[i] > kMaxAxis || p3[i] > kMaxAxis || m3[i] + 4 * p3[i] > kMaxAxis) return NDC_EUNSUPPORTED;
+    ny *= m3[i] + 2 * p3[i];
+    if (ny > kMaxElems) return NDC_EUNSUPPORTED;
+  }
+  // grid limits of the launches (y: 16-row tiles, z: output planes)
+  if (m3[0] + 2 * p3[0] > kMaxGridYZ || (m3[1] + 2 * p3[1] + 15) / 16 > kMaxGridYZ) return NDC_EUNSUPPORTED;
+  return NDC_OK;
+}
+
+size_t esize(int dtype) { return dtype == NDC_F64 ? sizeof(double) : sizeof(float); }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return na && nb && x < y + nb && y < x + na;
+}
+
+// A pointer the current device can dereference (device or managed memory).
+bool device_ptr(const void *ptr) {
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  hipError_t e = hipPointerGetAttributes(&at, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged || at.type == hipMemoryTypeUnified;
+}
+
+struct Extents {
+  int64_t m3[3], p3[3];
+  size_t nx, ny, nh;  // element counts
+};
+
+int prepare(int n, const int64_t *m, const int64_t *p, int dtype, int precision, Extents &E) {
+  int rc = check_problem(n, m, p, dtype, precision, E.m3, E.p3);
+  if (rc) return rc;
+  E.nx = E.ny = E.nh = 1;
+  for (int i = 0; i < 3; ++i) {
+    E.nx *= (size_t)E.m3[i];
+    E.ny *= (size_t)(E.m3[i] + 2 * E.p3[i]);
+    E.nh *= (size_t)(2 * E.p3[i] + 1);
+  }
+  return NDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ndc_strerror(int status) {
+  switch (status) {
+    case NDC_OK: return "success";
+    case NDC_EINVAL: return "invalid argument (rank, extent, half-width, count, pointer or scalar)";
+    case NDC_EUNSUPPORTED: return "valid request not supported by this build (rank > 3, sizes, or bf16 with FP64)";
+    case NDC_EALIAS: return "an output buffer overlaps an input or another output";
+    case NDC_ENONFINITE: return "non-finite objective";
+    case NDC_EDEVICE: return "HIP runtime or kernel launch failure";
+    case NDC_EWORKSPACE: return "workspace missing or too small";
+    default: return "unknown status";
+  }
+}
+
+int ndc_version(void) { return (1 << 16) | 0; }
+
+int conv_full_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *H, void *Y, int dtype,
+                 int precision, void *stream) {
+  Extents E;
+  int rc = prepare(n, m, p, dtype, precision, E);
+  if (rc) return rc;
+  if (!X || !H || !Y) return NDC_EINVAL;
+  const size_t es = esize(dtype);
+  if (overlap(Y, E.ny * es, X, E.nx * es) || overlap(Y, E.ny * es, H, E.nh * es)) return NDC_EALIAS;
+  if (!device_ptr(X) || !device_ptr(H) || !device_ptr(Y)) return NDC_EINVAL;
+  const Geom g = forward_geom(E.m3, E.p3);
+  const ConvPlan pl = plan_conv(g, dtype, precision);
+  Epi ep{};
+  ep.mode = EPI_STORE;
+  return launch_conv(pl, g, dtype, precision, X, H, Y, ep, (hipStream_t)stream) == hipSuccess ? NDC_OK
+                                                                                              : NDC_EDEVICE;
+}
+
+int conv_adjoint_nd(int n, const int64_t *m, const int64_t *p, const void *R, const void *H, void *X, int dtype,
+                    int precision, void *stream) {
+  Extents E;
+  int rc = prepare(n, m, p, dtype, precision, E);
+  if (rc) return rc;
+  if (!R || !H || !X) return NDC_EINVAL;
+  const size_t es = esize(dtype);
+  if (overlap(X, E.nx * es, R, E.ny * es) || overlap(X, E.nx * es, H, E.nh * es)) return NDC_EALIAS;
+  if (!device_ptr(R) || !device_ptr(H) || !device_ptr(X)) return NDC_EINVAL;
+  const Geom g = adjoint_geom(E.m3, E.p3);
+  const ConvPlan pl = plan_conv(g, dtype, precision);
+  Epi ep{};
+  ep.mode = EPI_STORE;
+  return launch_conv(pl, g, dtype, precision, R, H, X, ep, (hipStream_t)stream) == hipSuccess ? NDC_OK
+                                                                                              : NDC_EDEVICE;
+}
+
+// dH = valid correlation of G (extent m+2p) with X (extent m) as the taps:
+// output extent 2p+1.  Split-K over X's z-planes keeps the chip busy; the
+// per-split outputs go to the workspace and are summed in fixed order.
+static void dH_split(const int64_t m3[3], const int64_t p3[3], Geom &g, int &ksplit, int &zchunk) {
+  g.oz = (int)(2 * p3[0] + 1);
+  g.oy = (int)(2 * p3[1] + 1);
+  g.ox = (int)(2 * p3[2] + 1);
+  g.iz = (int)(m3[0] + 2 * p3[0]);
+  g.iy = (int)(m3[1] + 2 * p3[1]);
+  g.ix = (int)(m3[2] + 2 * p3[2]);
+  g.kz = (int)m3[0];
+  g.ky = (int)m3[1];
+  g.kx = (int)m3[2];
+  g.offz = g.offy = g.offx = 0;
+  g.flip = 0;
+  const dim3 base = valu_grid(g, 1);
+  const int64_t nb = grid_blocks(base);
+  int64_t s = (2048 + nb - 1) / nb;
+  if (s > g.kz) s = g.kz;
+  if (s * g.oz > kMaxGridYZ) s = kMaxGridYZ / g.oz;
+  if (s < 1) s = 1;
+  zchunk = (int)((g.kz + s - 1) / s);
+  ksplit = (g.kz + zchunk - 1) / zchunk;
+}
+
+size_t conv_dH_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype) {
+  Extents E;
+  if (prepare(n, m, p, dtype, NDC_PREC_NATIVE, E)) return 0;
+  Geom g;
+  int ks, zc;
+  dH_split(E.m3, E.p3, g, ks, zc);
+  return ks > 1 ? (size_t)ks * E.nh * esize(dtype) : 0;
+}
+
+int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH, int dtype,
+               void *ws, size_t ws_bytes, void *stream) {
+  Extents E;
+  int rc = prepare(n, m, p, dtype, NDC_PREC_NATIVE, E);
+  if (rc) return rc;
+  if (!X || !G || !dH) return NDC_EINVAL;
+  const size_t es = esize(dtype);
+  Geom g;
+  int ks, zc;
+  dH_split(E.m3, E.p3, g, ks, zc);
+  const size_t need = ks > 1 ? (size_t)ks * E.nh * es : 0;
+  if (need && (!ws || ws_bytes < need)) return NDC_EWORKSPACE;
+  if (overlap(dH, E.nh * es, X, E.nx * es) || overlap(dH, E.nh * es, G, E.ny * es)) return NDC_EALIAS;
+  if (need && (overlap(ws, need, X, E.nx * es) || overlap(ws, need, G, E.ny * es) || overlap(ws, need, dH, E.nh * es)))
+    return NDC_EALIAS;
+  if (!device_ptr(X) || !device_ptr(G) || !device_ptr(dH) || (need && !device_ptr(ws))) return NDC_EINVAL;
+  Epi ep{};
+  ep.mode = EPI_STORE;
+  hipStream_t s = (hipStream_t)stream;
+  if (ks == 1) {
+    if (launch_conv_valu(g, dtype, NDC_PREC_NATIVE, G, X, dH, ep, 1, g.kz, s) != hipSuccess) return NDC_EDEVICE;
+    return NDC_OK;
+  }
+  if (launch_conv_valu(g, dtype, NDC_PREC_NATIVE, G, X, ws, ep, ks, zc, s) != hipSuccess) return NDC_EDEVICE;
+  if (launch_splitk_reduce(dtype, ws, dH, (int64_t)E.nh, ks, s) != hipSuccess) return NDC_EDEVICE;
+  return NDC_OK;
+}
+
+size_t deconv_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype, int precision) {
+  Extents E;
+  if (prepare(n, m, p, dtype, precision, E)) return 0;
+  return deconv_ws_bytes(E.m3, E.p3, dtype, precision);
+}
+
+int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
+                   double lambda, int dtype, int precision, void *ws, size_t ws_bytes, double *stats, int *info,
+                   void *stream) {
+  Extents E;
+  int rc = prepare(n, m, p, dtype, precision, E);
+  if (rc) return rc;
+  if (!Y || !H || !X) return NDC_EINVAL;
+  if (iters < 0 || !(lambda >= 0.0) || !isfinite(lambda)) return NDC_EINVAL;
+  const size_t need = deconv_ws_bytes(E.m3, E.p3, dtype, precision);
+  if (!ws || ws_bytes < need) return NDC_EWORKSPACE;
+  const size_t es = esize(dtype);
+  const size_t ns = stats ? (size_t)4 * ((size_t)iters + 1) * sizeof(double) : 0;
+  const size_t ni = info ? 2 * sizeof(int) : 0;
+  // outputs: X, ws, stats, info; inputs: Y, H
+  const void *outs[4] = {X, ws, stats, info};
+  const size_t outn[4] = {E.nx * es, need, ns, ni};
+  for (int i = 0; i < 4; ++i) {
+    if (overlap(outs[i], outn[i], Y, E.ny * es) || overlap(outs[i], outn[i], H, E.nh * es)) return NDC_EALIAS;
+    for (int j = i + 1; j < 4; ++j)
+      if (overlap(outs[i], outn[i], outs[j], outn[j])) return NDC_EALIAS;
+  }
+  if (!device_ptr(Y) || !device_ptr(H) || !device_ptr(X) || !device_ptr(ws)) return NDC_EINVAL;
+  if ((stats && !device_ptr(stats)) || (info && !device_ptr(info))) return NDC_EINVAL;
+  return deconv_run(E.m3, E.p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,312 @@
+// Projected-gradient deconvolution (Steps 1-3 of the paper's algorithm) with
+// the step-size acceptance rule f(X^{k+1}) < f(X^k) decided on the device.
+//
+// One "step" is a fixed launch sequence whose kernels read the phase word in
+// device memory and return at once when they have nothing to do:
+//   1. transpose of R with the UPDATE epilogue   (phase NEW):   G, X_t, partials
+//   2. elementwise update with the halved delta  (phase RETRY): X_t, partials
+//   3. forward of X_t with the RESID epilogue    (NEW|RETRY):   R_t, partials
+//   4. decide (one work-group): f(X_t) < f(X^k) ? accept : halve delta
+//   5. commit (only right after an acceptance): X <- X_t, R <- R_t
+// Rejections happen only at rounding-level stationarity with the adopted
+// delta_0, so the host normally launches `iters` steps and waits once.
+#include <math.h>
+
+#include "ndc_device.h"
+#include "ndc_internal.h"
+
+namespace ndc {
+namespace {
+
+constexpr int ET = 256;          // elementwise work-group size
+constexpr int EW_MAX_BLOCKS = 1024;
+
+inline int64_t ew_blocks(int64_t n) {
+  int64_t b = (n + ET * 4 - 1) / (ET * 4);
+  return b < 1 ? 1 : (b > EW_MAX_BLOCKS ? EW_MAX_BLOCKS : b);
+}
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Deterministic one-work-group sum of part[stride*i + comp], i < cnt.
+__device__ double wg_sum(const double *part, int64_t cnt, int comp, double (*red)[2]) {
+  double s = 0.0, dummy = 0.0;
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) s += part[2 * i + comp];
+  block_sum2(s, dummy, red);
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+template <typename T>
+__global__ __launch_bounds__(ET) void init_kernel(const T *__restrict__ H, int64_t nh, double lambda, int iters,
+                                                  int jmax, DState *st) {
+  __shared__ double red[ET / 64][2];
+  double s = 0.0, dummy = 0.0;
+  for (int64_t i = threadIdx.x; i < nh; i += ET) s += fabs((double)H[i]);
+  block_sum2(s, dummy, red);
+  if (threadIdx.x == 0) {
+    st->delta0 = 1.0 / (s * s + lambda);
+    st->delta = st->delta0;
+    st->lambda = lambda;
+    st->f_cur = 0.0;
+    st->phase = PH_NEW;
+    st->k = 0;
+    st->rej = 0;
+    st->status = 0;
+    st->iters = iters;
+    st->jmax = jmax;
+    st->accepted = 0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(ET) void sumsq_kernel(const T *__restrict__ x, int64_t n, double *part) {
+  __shared__ double red[ET / 64][2];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < n; i += (int64_t)gridDim.x * ET) {
+    const double v = (double)x[i];
+    s0 += v * v;
+  }
+  block_sum2(s0, s1, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0;
+    part[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(ET) void f0_kernel(DState *st, const double *part_fwd, int64_t nf,
+                                                const double *part_x, int64_t nx, double *stats, int *info) {
+  __shared__ double red[ET / 64][2];
+  const double r2 = wg_sum(part_fwd, nf, 0, red);
+  const double x2 = wg_sum(part_x, nx, 0, red);
+  if (threadIdx.x == 0) {
+    const double f0 = 0.5 * r2 + 0.5 * st->lambda * x2;
+    st->f_cur = f0;
+    if (!isfinite(f0)) {
+      st->status = NDC_ENONFINITE;
+      st->phase = PH_DONE;
+    } else {
+      st->phase = st->iters > 0 ? PH_NEW : PH_DONE;
+    }
+    if (stats) {
+      stats[0] = f0;
+      stats[1] = NAN;
+      stats[2] = 0.0;
+      stats[3] = NAN;
+    }
+    if (info) {
+      info[0] = 0;
+      info[1] = st->status;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(ET) void update_kernel(const T *__restrict__ X, const T *__restrict__ G,
+                                                    T *__restrict__ Xt, int64_t n, const DState *st,
+                                                    double *part) {
+  if (st->phase != PH_RETRY) return;
+  __shared__ double red[ET / 64][2];
+  const T d = (T)st->delta;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < n; i += (int64_t)gridDim.x * ET) {
+    const T x = X[i];
+    const T xt = proj_nonneg<T>(x - d * G[i]);
+    Xt[i] = xt;
+    s0 += (double)xt * (double)xt;
+    const double dd = (double)xt - (double)x;
+    s1 += dd * dd;
+  }
+  block_sum2(s0, s1, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0;
+    part[2 * blockIdx.x + 1] = s1;
+  }
+}
+
+__global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *part_fwd, int64_t nf,
+                                                    const double *part_upd, int64_t n_adj, int64_t n_ew,
+                                                    double *stats, int *info) {
+  const int phase = st->phase;  // uniform
+  if (phase == PH_DONE) {
+    if (threadIdx.x == 0) st->accepted = 0;
+    return;
+  }
+  __shared__ double red[ET / 64][2];
+  const int64_t nu = phase == PH_NEW ? n_adj : n_ew;
+  const double r2 = wg_sum(part_fwd, nf, 0, red);
+  const double x2 = wg_sum(part_upd, nu, 0, red);
+  const double dx2 = wg_sum(part_upd, nu, 1, red);
+  if (threadIdx.x != 0) return;
+  const double ft = 0.5 * r2 + 0.5 * st->lambda * x2;
+  if (!isfinite(ft)) {
+    st->status = NDC_ENONFINITE;
+    st->phase = PH_DONE;
+    st->accepted = 0;
+  } else if (ft < st->f_cur) {
+    const int k = st->k + 1;
+    if (stats) {
+      stats[4 * k + 0] = ft;
+      stats[4 * k + 1] = st->delta;
+      stats[4 * k + 2] = (double)st->rej;
+      stats[4 * k + 3] = sqrt(dx2);
+    }
+    st->k = k;
+    st->f_cur = ft;
+    st->rej = 0;
+    st->delta = st->delta0;
+    st->accepted = 1;
+    st->phase = k >= st->iters ? PH_DONE : PH_NEW;
+  } else {
+    st->accepted = 0;
+    st->rej += 1;
+    st->delta *= 0.5;
+    if (st->rej >= st->jmax) {
+      st->status = 1;
+      st->phase = PH_DONE;
+    } else {
+      st->phase = PH_RETRY;
+    }
+  }
+  if (info) {
+    info[0] = st->k;
+    info[1] = st->status;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(ET) void commit_kernel(const DState *st, T *__restrict__ X, const T *__restrict__ Xt,
+                                                    int64_t n, T *__restrict__ R, const T *__restrict__ Rt,
+                                                    int64_t ny) {
+  if (!st->accepted) return;
+  const int64_t m = n > ny ? n : ny;
+  for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < m; i += (int64_t)gridDim.x * ET) {
+    if (i < n) X[i] = Xt[i];
+    if (i < ny) R[i] = Rt[i];
+  }
+}
+
+struct WsLayout {
+  size_t state, part_fwd, part_upd, xt, g, r, rt, total;
+};
+
+WsLayout layout(int64_t N, int64_t NY, size_t esz, int64_t nf, int64_t nu) {
+  WsLayout L;
+  size_t o = 0;
+  L.state = o;
+  o += align256(sizeof(DState));
+  L.part_fwd = o;
+  o += align256((size_t)nf * 2 * sizeof(double));
+  L.part_upd = o;
+  o += align256((size_t)nu * 2 * sizeof(double));
+  L.xt = o;
+  o += align256((size_t)N * esz);
+  L.g = o;
+  o += align256((size_t)N * esz);
+  L.r = o;
+  o += align256((size_t)NY * esz);
+  L.rt = o;
+  o += align256((size_t)NY * esz);
+  L.total = o;
+  return L;
+}
+
+struct Sizes {
+  int64_t N, NY, NH;
+  Geom gf, ga;
+  ConvPlan pf, pa;
+  int64_t n_ew;
+};
+
+Sizes sizes_for(const int64_t m3[3], const int64_t p3[3], int dtype, int precision) {
+  Sizes s;
+  s.N = m3[0] * m3[1] * m3[2];
+  s.NY = (m3[0] + 2 * p3[0]) * (m3[1] + 2 * p3[1]) * (m3[2] + 2 * p3[2]);
+  s.NH = (2 * p3[0] + 1) * (2 * p3[1] + 1) * (2 * p3[2] + 1);
+  s.gf = forward_geom(m3, p3);
+  s.ga = adjoint_geom(m3, p3);
+  s.pf = plan_conv(s.gf, dtype, precision);
+  s.pa = plan_conv(s.ga, dtype, precision);
+  s.n_ew = ew_blocks(s.N);
+  return s;
+}
+
+template <typename T>
+int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *Xv, int iters,
+             double lambda, int dtype, int precision, void *ws, double *stats, int *info, hipStream_t s) {
+  const Sizes S = sizes_for(m3, p3, dtype, precision);
+  const int64_t nu = S.pa.nblocks > S.n_ew ? S.pa.nblocks : S.n_ew;
+  const WsLayout L = layout(S.N, S.NY, sizeof(T), S.pf.nblocks, nu);
+  char *w = (char *)ws;
+  DState *st = (DState *)(w + L.state);
+  double *part_fwd = (double *)(w + L.part_fwd);
+  double *part_upd = (double *)(w + L.part_upd);
+  T *X = (T *)Xv, *Xt = (T *)(w + L.xt), *G = (T *)(w + L.g), *R = (T *)(w + L.r), *Rt = (T *)(w + L.rt);
+
+  hipLaunchKernelGGL(init_kernel<T>, dim3(1), dim3(ET), 0, s, (const T *)H, S.NH, lambda, iters, 30, st);
+  hipLaunchKernelGGL(sumsq_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, S.N, part_upd);
+  Epi ef{};
+  ef.mode = EPI_RESID;
+  ef.Y = Y;
+  ef.part = part_fwd;
+  ef.phase = nullptr;
+  if (launch_conv(S.pf, S.gf, dtype, precision, X, H, R, ef, s) != hipSuccess) return NDC_EDEVICE;
+  hipLaunchKernelGGL(f0_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_fwd, S.pf.nblocks,
+                     (const double *)part_upd, S.n_ew, stats, info);
+  if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
+
+  Epi ea{};
+  ea.mode = EPI_UPDATE;
+  ea.X = X;
+  ea.G = G;
+  ea.lambda = lambda;
+  ea.delta = &st->delta;
+  ea.part = part_upd;
+  ea.phase = &st->phase;
+  ea.phase_mask = 1 << PH_NEW;
+  Epi et{};
+  et.mode = EPI_RESID;
+  et.Y = Y;
+  et.part = part_fwd;
+  et.phase = &st->phase;
+  et.phase_mask = (1 << PH_NEW) | (1 << PH_RETRY);
+  const int64_t ncommit = ew_blocks(S.NY > S.N ? S.NY : S.N);
+
+  int remaining = iters;
+  while (remaining > 0) {
+    for (int step = 0; step < remaining; ++step) {
+      if (launch_conv(S.pa, S.ga, dtype, precision, R, H, Xt, ea, s) != hipSuccess) return NDC_EDEVICE;
+      hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, (const T *)G, Xt,
+                         S.N, (const DState *)st, part_upd);
+      if (launch_conv(S.pf, S.gf, dtype, precision, Xt, H, Rt, et, s) != hipSuccess) return NDC_EDEVICE;
+      hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_fwd, S.pf.nblocks,
+                         (const double *)part_upd, S.pa.nblocks, S.n_ew, stats, info);
+      hipLaunchKernelGGL(commit_kernel<T>, dim3((unsigned)ncommit), dim3(ET), 0, s, (const DState *)st, X,
+                         (const T *)Xt, S.N, R, (const T *)Rt, S.NY);
+      if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
+    }
+    DState h;
+    if (hipMemcpyAsync(&h, st, sizeof(DState), hipMemcpyDeviceToHost, s) != hipSuccess) return NDC_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return NDC_EDEVICE;
+    if (h.phase == PH_DONE) break;
+    remaining = iters - h.k;
+  }
+  return NDC_OK;
+}
+
+}  // namespace
+
+size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision) {
+  const Sizes S = sizes_for(m3, p3, dtype, precision);
+  const int64_t nu = S.pa.nblocks > S.n_ew ? S.pa.nblocks : S.n_ew;
+  const size_t esz = dtype == NDC_F64 ? sizeof(double) : sizeof(float);
+  return layout(S.N, S.NY, esz, S.pf.nblocks, nu).total;
+}
+
+int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
+               double lambda, int dtype, int precision, void *ws, double *stats, int *info, hipStream_t s) {
+  if (dtype == NDC_F64) return deconv_t<double>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, s);
+  return deconv_t<float>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, s);
+}
+
+}  // namespace ndc

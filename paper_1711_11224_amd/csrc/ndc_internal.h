@@ -1,0 +1,83 @@
+// Internal declarations of the gfx950 convolution library.  Not part of the
+// C ABI (that is include/ndconv.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ndconv.h"
+
+namespace ndc {
+
+// Both operators are one correlation over a zero-extended input:
+//   out[s] = sum_{t in [0,k)} Hc[t] * in[s + t - off]   (in = 0 outside [0,in_extent))
+// Forward (Property 1): out extent m+2p, in = X (extent m), off = 2p and
+//   Hc[t] = H[2p - t] (so the sum is sum_j H[j] X[s - j]).
+// Transpose (Property 2): out extent m, in = R (extent m+2p), off = 0 and
+//   Hc = H (every tap lands inside R).
+struct Geom {
+  int oz, oy, ox;        // output extent
+  int iz, iy, ix;        // input extent
+  int kz, ky, kx;        // tap extent (2p+1)
+  int offz, offy, offx;  // input index = out + tap - off
+  int flip;              // Hc[t] = H[k-1-t] on every axis
+};
+
+enum EpiMode { EPI_STORE = 0, EPI_RESID = 1, EPI_UPDATE = 2 };
+
+// Deconvolution phases kept on the device (see deconv.hip).
+enum Phase { PH_NEW = 0, PH_RETRY = 1, PH_DONE = 2 };
+
+// Epilogue applied to each output value `acc` at flat index i:
+//   STORE : out[i] = acc
+//   RESID : r = acc - Y[i]; out[i] = r; part0 += r^2            (objective)
+//   UPDATE: g = acc + lambda*X[i]; G[i] = g;
+//           xt = max(X[i] - delta*g, 0); out[i] = xt;
+//           part0 += xt^2, part1 += (xt - X[i])^2               (Step 2)
+// Partial sums are double, one pair per work-group, written without atomics.
+// If phase != nullptr the kernel runs only when (1 << *phase) & phase_mask.
+struct Epi {
+  int mode;
+  const void *Y;
+  const void *X;
+  void *G;
+  double lambda;
+  const double *delta;
+  double *part;
+  const int *phase;
+  int phase_mask;
+};
+
+struct DState {
+  double f_cur;    // f(X^k)
+  double delta;    // trial step of the current attempt
+  double delta0;   // 1/(||H||_1^2 + lambda)
+  double lambda;
+  int phase;       // Phase
+  int k;           // accepted steps
+  int rej;         // rejected trials in the current step
+  int status;      // 0, 1 (no descent) or NDC_ENONFINITE
+  int iters;       // target accepted steps
+  int jmax;        // trials per step
+  int accepted;    // 1 right after an accepting decision (commit copies)
+  int pad;
+};
+
+// Launch descriptors --------------------------------------------------------
+struct ConvPlan {
+  int variant;        // 0 = VALU direct, 1 = MFMA
+  dim3 grid, block;
+  size_t lds_bytes;
+  int64_t nblocks;    // number of work-groups (partial-sum slots)
+};
+
+// Fold an n-D problem (n <= 3) into 3-D extents.
+bool fold3(int n, const int64_t *m, const int64_t *p, int64_t m3[3], int64_t p3[3]);
+Geom forward_geom(const int64_t m3[3], const int64_t p3[3]);
+Geom adjoint_geom(const int64_t m3[3], const int64_t p3[3]);
+
+// Plans and launches (conv_*.hip).  Return hipSuccess or the launch error.
+ConvPlan plan_conv(const Geom &g, int dtype, int precision);
+hipError_t launch_conv(const ConvPlan &pl, const Geom &g, int dtype, int precision, const void *in,
+                       const void *H, void *out, const Epi &ep, hipStream_t s);
+
+}  // namespace ndc

@@ -1,0 +1,112 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+nd = pytest.importorskip("paper_1711_11224_amd._native")
+lib = nd.lib
+I = nd.i64_array
+F32, F64 = nd.NDC_F32, nd.NDC_F64
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "ndconv.h")).read()
+    src = src.split("extern \"C\" {", 1)[1]
+    return re.findall(r"NDC_API\s+[\w\s\*]*?\b(\w+)\s*\(", src)
+
+
+def test_exports_every_header_symbol():
+    syms = header_symbols()
+    assert set(syms) == set(nd.EXPORTS)
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_version_and_strerror():
+    assert lib.ndc_version() >> 16 == 1
+    for code in (0, -1, -2, -3, -4, -5, -6, 99):
+        assert isinstance(nd.strerror(code), str) and nd.strerror(code)
+    assert nd.strerror(99) == "unknown status"
+
+
+def _full(n, m, p, X=0x1000, H=0x100000, Y=0x10000000, dt=F32, pr=0):
+    return lib.conv_full_nd(n, I(m), I(p), ctypes.c_void_p(X), ctypes.c_void_p(H), ctypes.c_void_p(Y), dt, pr, None)
+
+
+def _adj(n, m, p, R=0x1000, H=0x100000000, X=0x10000000, dt=F32, pr=0):
+    return lib.conv_adjoint_nd(n, I(m), I(p), ctypes.c_void_p(R), ctypes.c_void_p(H), ctypes.c_void_p(X), dt, pr,
+                               None)
+
+
+@pytest.mark.parametrize("fn", [_full, _adj])
+def test_rank_extent_and_halfwidth_checks(fn):
+    assert fn(0, [4], [1]) == nd.NDC_EINVAL
+    assert fn(4, [2, 2, 2, 2], [0, 0, 0, 0]) == nd.NDC_EUNSUPPORTED
+    assert fn(2, [0, 4], [1, 1]) == nd.NDC_EINVAL
+    assert fn(2, [4, 4], [1, -1]) == nd.NDC_EINVAL
+    assert fn(1, [1 << 30], [0]) == nd.NDC_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("fn", [_full, _adj])
+def test_dtype_precision_checks(fn):
+    assert fn(2, [4, 4], [1, 1], dt=7) == nd.NDC_EINVAL
+    assert fn(2, [4, 4], [1, 1], pr=9) == nd.NDC_EINVAL
+    assert fn(2, [4, 4], [1, 1], dt=F64, pr=nd.NDC_PREC_BF16) == nd.NDC_EUNSUPPORTED
+    assert fn(2, [4, 4], [1, 1], dt=F64, pr=nd.NDC_PREC_SPLIT_BF16) == nd.NDC_EUNSUPPORTED
+
+
+def test_null_and_alias_checks():
+    assert _full(2, [4, 4], [1, 1], X=0) == nd.NDC_EINVAL
+    assert _full(2, [4, 4], [1, 1], H=0) == nd.NDC_EINVAL
+    assert _full(2, [4, 4], [1, 1], Y=0) == nd.NDC_EINVAL
+    # Y (6x6 floats = 144 B) overlapping X
+    assert _full(2, [4, 4], [1, 1], X=0x1000, Y=0x1000 + 32) == nd.NDC_EALIAS  # X is 64 B
+    # Y overlapping H
+    assert _full(2, [4, 4], [1, 1], H=0x2000, Y=0x2000 - 100) == nd.NDC_EALIAS
+    assert _adj(2, [4, 4], [1, 1], R=0x1000, X=0x1000 + 140) == nd.NDC_EALIAS
+
+
+def test_workspace_queries():
+    assert lib.deconv_workspace_bytes(3, I([8, 9, 10]), I([1, 2, 3]), F32, 0) > 0
+    assert lib.deconv_workspace_bytes(3, I([8, 9, 10]), I([1, 2, -3]), F32, 0) == 0
+    assert lib.deconv_workspace_bytes(3, I([8, 9, 10]), I([1, 2, 3]), F64, nd.NDC_PREC_BF16) == 0
+    a = lib.deconv_workspace_bytes(3, I([8, 9, 10]), I([1, 2, 3]), F32, 0)
+    b = lib.deconv_workspace_bytes(3, I([8, 9, 10]), I([1, 2, 3]), F64, 0)
+    assert b > a  # double buffers
+    assert lib.conv_dH_workspace_bytes(3, I([8, 9, 10]), I([1, 2, 3]), F32) >= 0
+
+
+def _deconv(iters=3, lam=0.0, ws=0x40000000, wsb=None, stats=0, info=0, X=0x1000):
+    m, p = [4, 5, 6], [1, 1, 1]
+    need = lib.deconv_workspace_bytes(3, I(m), I(p), F32, 0)
+    return lib.deconv_iterate(3, I(m), I(p), ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000),
+                              ctypes.c_void_p(X), iters, lam, F32, 0, ctypes.c_void_p(ws),
+                              need if wsb is None else wsb, ctypes.c_void_p(stats) if stats else None,
+                              ctypes.c_void_p(info) if info else None, None)
+
+
+def test_deconv_argument_checks():
+    assert _deconv(iters=-1) == nd.NDC_EINVAL
+    assert _deconv(lam=-1.0) == nd.NDC_EINVAL
+    assert _deconv(lam=float("nan")) == nd.NDC_EINVAL
+    assert _deconv(lam=float("inf")) == nd.NDC_EINVAL
+    assert _deconv(ws=0) == nd.NDC_EWORKSPACE
+    assert _deconv(wsb=16) == nd.NDC_EWORKSPACE
+    assert _deconv(X=0) == nd.NDC_EINVAL
+    # X overlapping the workspace, stats overlapping Y
+    assert _deconv(X=0x40000000 + 8) == nd.NDC_EALIAS
+    assert _deconv(stats=0x10000000 + 8) == nd.NDC_EALIAS
+
+
+def test_dH_workspace_check():
+    m, p = [16, 64, 64], [3, 4, 5]
+    need = lib.conv_dH_workspace_bytes(3, I(m), I(p), F32)
+    assert need > 0  # split-K partial outputs
+    rc = lib.conv_dH_nd(3, I(m), I(p), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x10000000),
+                        ctypes.c_void_p(0x20000000), F32, None, 0, None)
+    assert rc == nd.NDC_EWORKSPACE

@@ -1,0 +1,208 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle on the
+same seeded inputs.  Tolerances are relative L2 errors: 1e-5 for FP32,
+1e-12 for FP64, 1e-2 for bf16 and 1e-4 for split-bf16 operands; shapes and
+crop extents must match exactly."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "fp64": 1e-12, "bf16": 1e-2, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def nd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1711_11224_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (den if den > 0 else 1.0)
+
+
+def gpu(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+# Shapes spanning several tiles, ragged tails, 2p >= m, unit extents, n = 1..3.
+CASES = [
+    ((5, 37, 70), (2, 3, 4)),
+    ((3, 16, 64), (1, 0, 2)),
+    ((2, 3, 130), (3, 5, 1)),
+    ((1, 1, 1), (0, 0, 0)),
+    ((4, 20, 9), (0, 2, 7)),
+    ((70,), (5,)),
+    ((33, 47), (4, 6)),
+    ((7, 19, 150), (3, 9, 15)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("m,p", CASES)
+def test_conv_full_and_adjoint(nd, m, p, dtype):
+    say("case conv m=%s p=%s %s" % (m, p, dtype))
+    rng = np.random.default_rng(hash((m, p)) % 2**32)
+    npdt = np.float32 if dtype == "fp32" else np.float64
+    h = rng.standard_normal([2 * q + 1 for q in p]).astype(npdt)  # asymmetric, signed
+    x = rng.random(m).astype(npdt)
+    y = nd.conv_full_nd(gpu(x, npdt), gpu(h, npdt)).cpu().numpy()
+    yo = oracle.conv_full(x, h)
+    assert y.shape == yo.shape
+    assert rel_l2(y, yo) <= TOL[dtype]
+    r = rng.standard_normal(yo.shape).astype(npdt)
+    g = nd.conv_adjoint_nd(gpu(r, npdt), gpu(h, npdt)).cpu().numpy()
+    go = oracle.conv_adjoint(r, h)
+    assert g.shape == tuple(m)
+    assert rel_l2(g, go) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
+@pytest.mark.parametrize("m,p", [((5, 37, 70), (2, 3, 4)), ((6, 40, 100), (3, 7, 15)), ((33, 47), (4, 6))])
+def test_reduced_precision(nd, m, p, prec):
+    say("case prec m=%s p=%s %s" % (m, p, prec))
+    rng = np.random.default_rng(11)
+    h = rng.random([2 * q + 1 for q in p]).astype(np.float32)
+    h /= h.sum()
+    x = rng.random(m).astype(np.float32)
+    y = nd.conv_full_nd(gpu(x, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
+    assert rel_l2(y, oracle.conv_full(x, h)) <= TOL[prec]
+    r = rng.standard_normal(y.shape).astype(np.float32)
+    g = nd.conv_adjoint_nd(gpu(r, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
+    assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("m,p", [((6, 9, 11), (1, 2, 3)), ((16, 40, 40), (3, 2, 4)), ((20, 33), (2, 5))])
+def test_conv_dH(nd, m, p, dtype):
+    say("case dH m=%s p=%s %s" % (m, p, dtype))
+    rng = np.random.default_rng(5)
+    npdt = np.float32 if dtype == "fp32" else np.float64
+    x = rng.random(m).astype(npdt)
+    gr = rng.standard_normal([a + 2 * b for a, b in zip(m, p)]).astype(npdt)
+    ps = [2 * q + 1 for q in p]
+    dh = nd.conv_dH_nd(gpu(x, npdt), gpu(gr, npdt), ps).cpu().numpy()
+    assert rel_l2(dh, oracle.conv_dH(x, gr, ps)) <= TOL[dtype]
+
+
+def test_deterministic(nd):
+    rng = np.random.default_rng(3)
+    x = gpu(rng.random((9, 50, 80)), np.float32)
+    h = gpu(rng.random((7, 5, 9)), np.float32)
+    a = nd.conv_full_nd(x, h)
+    b = nd.conv_full_nd(x, h)
+    assert torch.equal(a, b)
+    c = nd.conv_adjoint_nd(a, h)
+    d = nd.conv_adjoint_nd(b, h)
+    assert torch.equal(c, d)
+
+
+def test_errors_on_device(nd):
+    x = torch.zeros((4, 4), device="cuda")
+    h = torch.zeros((3, 3), device="cuda")
+    with pytest.raises(TypeError):
+        nd.conv_full_nd(x.cpu(), h)
+    import ctypes
+    lib = nd.lib
+    host = np.zeros(36, dtype=np.float32)
+    rc = lib.conv_full_nd(2, nd.i64_array([4, 4]), nd.i64_array([1, 1]), ctypes.c_void_p(x.data_ptr()),
+                          ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(host.ctypes.data), 0, 0, None)
+    assert rc == -1  # host output pointer rejected before any launch
+    y = torch.zeros((6, 6), device="cuda")
+    rc = lib.conv_full_nd(2, nd.i64_array([4, 4]), nd.i64_array([1, 1]), ctypes.c_void_p(y.data_ptr()),
+                          ctypes.c_void_p(h.data_ptr()), ctypes.c_void_p(y.data_ptr() + 8), 0, 0, None)
+    assert rc == -3
+
+
+# ---------------------------------------------------------------- deconvolution
+def _check_deconv(nd, y, h, x0, iters, lam, npdt, tol_x, tol_f, prec="native"):
+    xg, st, info = nd.deconv_iterate(gpu(y, npdt), gpu(h, npdt), gpu(x0, npdt), iters, lam=lam, precision=prec)
+    torch.cuda.synchronize()
+    xo, so, done, status = oracle.deconv(y.astype(np.float64), h.astype(np.float64), x0.astype(np.float64),
+                                         iters, lam=lam)
+    inf = info.cpu().numpy()
+    stg = st.cpu().numpy()
+    assert int(inf[0]) == done and int(inf[1]) == status
+    # the accept/reject decisions must agree exactly; delta_0 = 1/||H||_1^2 is a
+    # double sum taken in a different order on each side, so allow rounding
+    np.testing.assert_array_equal(stg[1:done + 1, 2], so[1:done + 1, 2])
+    np.testing.assert_allclose(stg[1:done + 1, 1], so[1:done + 1, 1], rtol=1e-14, atol=0)
+    assert rel_l2(xg.cpu().numpy(), xo) <= tol_x
+    f_g, f_o = stg[:done + 1, 0], so[:done + 1, 0]
+    assert np.all(np.abs(f_g - f_o) <= tol_f * np.abs(f_o))
+    assert np.all(np.diff(f_g) < 0)
+    assert np.all(xg.cpu().numpy() >= 0)
+    return xg, stg, inf
+
+
+def test_deconv_c1_fp64_full(nd):
+    """2-D, FP64, 64x64 X, 9x9 PSF, Poisson at peak 1000, 50 iterations."""
+    cfg = synth.CONFIGS["c1_2d_f64"]
+    say("case deconv c1")
+    x_true = synth.make_objects(cfg)
+    h = synth.psf_for(cfg)
+    y = synth.add_noise(oracle.conv_full(x_true, h), cfg)
+    x0 = synth.flat_start(y, h, cfg.shape)
+    _check_deconv(nd, y, h, x0, cfg.iters, 0.0, np.float64, 1e-10, 1e-12)
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_deconv_fp32_small(nd, lam):
+    say("case deconv fp32 small lam=%g" % lam)
+    rng = np.random.default_rng(21)
+    m, p = (6, 24, 70), (2, 3, 5)
+    h = synth.gaussian_psf([2 * q + 1 for q in p], (1.0, 1.5, 2.0)).astype(np.float32)
+    x_true = rng.random(m)
+    y = (oracle.conv_full(x_true, h) + 0.05 * rng.standard_normal([a + 2 * b for a, b in zip(m, p)]))
+    y = y.astype(np.float32)
+    x0 = np.full(m, 0.4, dtype=np.float32)
+    _check_deconv(nd, y, h, x0, 20, lam, np.float32, 1e-5, 1e-5)
+
+
+def test_deconv_stops_without_descent(nd):
+    """Y = A X^0 exactly (integers, exact in FP32): f(X^0) = 0, no step can
+    decrease it, the loop stops with status 1 after 30 halvings."""
+    rng = np.random.default_rng(2)
+    h = rng.integers(1, 4, (3, 3, 3)).astype(np.float32)
+    x0 = rng.integers(0, 3, (4, 5, 6)).astype(np.float32)
+    y = oracle.conv_full(x0, h).astype(np.float32)
+    xg, st, info = nd.deconv_iterate(gpu(y, np.float32), gpu(h, np.float32), gpu(x0, np.float32), 3)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 1]
+    np.testing.assert_array_equal(xg.cpu().numpy(), x0)
+
+
+def test_deconv_nonfinite(nd):
+    h = np.full((3, 3), 1 / 9, dtype=np.float32)
+    y = np.ones((6, 6), dtype=np.float32)
+    y[2, 2] = np.nan
+    xg, st, info = nd.deconv_iterate(gpu(y, np.float32), gpu(h, np.float32), gpu(np.zeros((4, 4)), np.float32), 3)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, -4]
+
+
+def test_deconv_resume_is_exact(nd):
+    """The adopted step rule is stateless: 6 steps equal 3 + 3 bitwise."""
+    rng = np.random.default_rng(8)
+    m, p = (5, 30, 40), (1, 3, 3)
+    h = synth.gaussian_psf([3, 7, 7], (1.0, 1.2, 1.2)).astype(np.float32)
+    y = gpu(oracle.conv_full(rng.random(m), h) + 0.01, np.float32)
+    hg = gpu(h, np.float32)
+    xa, _, _ = nd.deconv_iterate(y, hg, torch.full(m, 0.3, device="cuda"), 6)
+    xb, _, _ = nd.deconv_iterate(y, hg, torch.full(m, 0.3, device="cuda"), 3)
+    xb, _, _ = nd.deconv_iterate(y, hg, xb, 3)
+    assert torch.equal(xa, xb)
