@@ -1,0 +1,202 @@
+"""Benchmark of the deconvolution hot path on one MI355X.
+
+Workload: a synthetic 128x512x512 (z, y, x) microscopy-like volume (8000
+points, 400 filaments), Gaussian PSF 63x31x31 (sigma_z 9, sigma_xy 3),
+Y = X (x) H plus Poisson (peak 500) and N(0, 2^2) read noise, FP32, lambda 0.
+
+One step = one projected-gradient iteration: transpose of the residual with
+the fused gradient/projection epilogue, forward convolution of the trial with
+the fused residual/objective epilogue, the device-side acceptance decision
+and the commit.  Algorithmic work per step: 2 N K multiply-adds (N = 33.5M
+voxels, K = 60543 taps), zero-padding products not counted.
+
+Prints one JSON line (see the design doc for the field definitions).
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3, "bf16": 2500.0, "split_bf16": 2500.0 / 3.0, "hbm": 8000.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def make_inputs(nd, torch, cfg, dev):
+    import synth
+    t = time.time()
+    x_true = synth.make_objects(cfg)
+    h = synth.psf_for(cfg).astype(np.float32)
+    xg = torch.from_numpy(x_true.astype(np.float32)).to(dev)
+    hg = torch.from_numpy(h).to(dev)
+    blurred = nd.conv_full_nd(xg, hg).cpu().numpy()
+    y = synth.add_noise(blurred, cfg).astype(np.float32)
+    x0 = synth.flat_start(y, h, cfg.shape).astype(np.float32)
+    log("inputs ready in %.1fs" % (time.time() - t))
+    return (torch.from_numpy(y).to(dev), hg, torch.from_numpy(x0).to(dev))
+
+
+def time_pairs(nd, torch, x, h, precision, reps):
+    """Average duration of each operator launch, HIP events on the stream the
+    library launches on (torch's current stream)."""
+    s = torch.cuda.current_stream()
+    y = nd.conv_full_nd(x, h, precision=precision)
+    g = nd.conv_adjoint_nd(y, h, precision=precision)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b, c in ev:
+        a.record(s)
+        nd.conv_full_nd(x, h, Y=y, precision=precision)
+        b.record(s)
+        nd.conv_adjoint_nd(y, h, X=g, precision=precision)
+        c.record(s)
+    torch.cuda.synchronize()
+    fwd = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    adj = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    return fwd, adj
+
+
+def cpu_baseline(cfg, target_s=15.0):
+    """The FP64 oracle, as it stands, on a bounded random sample of forward
+    and transpose outputs of the same workload (each output is a full
+    K-tap sum)."""
+    import oracle
+    import synth
+    rng = np.random.default_rng(99)
+    m, ks = cfg.shape, cfg.psf_shape
+    p = [(k - 1) // 2 for k in ks]
+    x = rng.random(m)
+    h = synth.psf_for(cfg)
+    r = rng.standard_normal([a + 2 * b for a, b in zip(m, p)])
+    K = int(np.prod(ks))
+    nthreads = oracle.threads()
+    # interior forward outputs (every tap in range) and any transpose output
+    def interior(cnt):
+        idx = [rng.integers(2 * q, a, size=cnt) for a, q in zip(m, p)]
+        return np.ravel_multi_index(idx, [a + 2 * b for a, b in zip(m, p)])
+    n = 64
+    while True:
+        t0 = time.time()
+        oracle.conv_full_at(x, h, interior(n))
+        oracle.conv_adjoint_at(r, h, rng.integers(0, int(np.prod(m)), size=n))
+        dt = time.time() - t0
+        if dt >= target_s or n >= 1 << 22:
+            break
+        n = int(n * min(8.0, max(2.0, 1.2 * target_s / max(dt, 1e-3))))
+    macs = 2.0 * n * K
+    return {"value": macs / dt / 1e9, "unit": "GMAC/s", "cores": nthreads, "kind": "oracle",
+            "sample": "%d forward + %d transpose outputs of the 128x512x512 / 63x31x31 workload, %d taps each, "
+                      "FP64 (%.1f s on %s)" % (n, n, K, dt, cpu_model())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "split_bf16"])
+    ap.add_argument("--pair-reps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precisions", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the hot path here is single-GPU (no collectives); "
+              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1711_11224_amd as nd
+    import synth
+
+    dev = torch.device("cuda:0")
+    cfg = synth.CONFIGS["c3_metric"]
+    N = int(np.prod(cfg.shape))
+    K = int(np.prod(cfg.psf_shape))
+    y, h, x0 = make_inputs(nd, torch, cfg, dev)
+    prec = args.precision
+
+    # untimed warm-up steps, then exactly `steps` timed steps
+    x = x0.clone()
+    nbytes = nd.deconv_workspace_bytes(cfg.shape, cfg.psf_shape, torch.float32, prec)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    if args.warmup > 0:
+        nd.deconv_iterate(y, h, x, args.warmup, precision=prec, ws=ws)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_host = time.perf_counter()
+    e0.record(s)
+    _, stats, info = nd.deconv_iterate(y, h, x, args.steps, precision=prec, ws=ws)
+    e1.record(s)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms = e0.elapsed_time(e1)
+    done, status = [int(v) for v in info.cpu().tolist()]
+    if done != args.steps:
+        log("warning: %d of %d steps accepted (status %d)" % (done, args.steps, status))
+    f = stats.cpu().numpy()[: done + 1, 0]
+    log("deconv: %d steps in %.1f ms (host %.1f ms), f %.6g -> %.6g" % (args.steps, ms, t_host * 1e3, f[0], f[-1]))
+    macs = 2.0 * N * K * done
+    value = macs / (ms * 1e-3) / 1e9
+
+    # per-kernel launch durations of the two operators (same kernels as the steps)
+    fwd_ms, adj_ms = time_pairs(nd, torch, x, h, prec, args.pair_reps)
+    pair_gmacs = 2.0 * N * K / ((fwd_ms + adj_ms) * 1e-3) / 1e9
+    log("pair %s: forward %.2f ms, transpose %.2f ms, %.0f GMAC/s" % (prec, fwd_ms, adj_ms, pair_gmacs))
+    dom_ms = max(fwd_ms, adj_ms)
+    achieved = 2.0 * N * K / (dom_ms * 1e-3) / 1e12
+    peak = PEAK[prec]
+    roofline = {"bound": "mfma" if os.environ.get("NDC_BOUND", "mfma") == "mfma" else "alu",
+                "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "forward" if fwd_ms >= adj_ms else "transpose",
+                "kernel_ms": round(dom_ms, 3)}
+
+    precisions = {}
+    if not args.no_precisions:
+        for pr in ("fp32", "bf16", "split_bf16"):
+            fm, am = time_pairs(nd, torch, x, h, pr, 3)
+            precisions[pr] = {"forward_ms": round(fm, 3), "transpose_ms": round(am, 3),
+                              "gmacs": round(2.0 * N * K / ((fm + am) * 1e-3) / 1e9, 1)}
+            log("pair %s: %.2f + %.2f ms" % (pr, fm, am))
+
+    out = {
+        "metric": "GMAC/s of 3-D full conv+adjoint and deconv iterations/s at 512²×128, PSF 31²×63",
+        "value": round(value, 1), "unit": "GMAC/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms / max(1, args.steps), 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16", "split_bf16": "bf16x3"}[prec],
+        "data": "synthetic",
+        "config": {"workload": "3-D deconvolution, X 128x512x512 (z,y,x), PSF 63x31x31, FP32 storage, lambda 0",
+                   "precision": prec, "steps_accepted": done, "iters_per_s": round(done / (ms * 1e-3), 3),
+                   "conv_pair_gmacs": round(pair_gmacs, 1), "macs_per_step": 2 * N * K},
+        "roofline": roofline,
+        "precisions": precisions,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
