@@ -77,6 +77,26 @@ def time_pairs(nd, torch, x, h, precision, reps):
     return fwd, adj
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    passes (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known
+    size), or None when the kernel sources changed since they were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_conv_128x512x512_psf63x31x31.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1711_11224_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    k = rec.get("kernels", {}).get(kernel_key)
+    if rec.get("csrc_sha256") != h.hexdigest() or not k:
+        return None
+    return int(k["read_bytes"] + k["write_bytes"])
+
+
 def cpu_baseline(cfg, target_s=15.0):
     """The FP64 oracle, as it stands, on a bounded random sample of forward
     and transpose outputs of the same workload (each output is a full
@@ -119,6 +139,8 @@ def main():
     ap.add_argument("--pair-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precisions", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path here is single-GPU (no collectives); "
@@ -134,6 +156,14 @@ def main():
     N = int(np.prod(cfg.shape))
     K = int(np.prod(cfg.psf_shape))
     y, h, x0 = make_inputs(nd, torch, cfg, dev)
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (nb, nb))
+        del src, dst
     prec = args.precision
 
     # untimed warm-up steps, then exactly `steps` timed steps
@@ -170,8 +200,13 @@ def main():
     roofline = {"bound": "mfma" if os.environ.get("NDC_BOUND", "mfma") == "mfma" else "alu",
                 "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": None,
+                "traffic_unit": "bytes per launch",
                 "kernel": "forward" if fwd_ms >= adj_ms else "transpose",
                 "kernel_ms": round(dom_ms, 3)}
+
+    if prec == "fp32":
+        key = "void ndc::conv_mfma_f32_kernel<31>/%d" % (3760128 if fwd_ms >= adj_ms else 2097152)
+        roofline["traffic"] = measured_traffic(key)
 
     precisions = {}
     if not args.no_precisions:
