@@ -16,6 +16,7 @@ Functions and the passage each follows:
   conv_adjoint_literal Property 2, Eq. 2: crop M_{2p} of Y (x) H~
   conv_dH              gradient of 1/2||X(x)H - Y||^2 in H (Property 1 with the
                        roles of X and H swapped)
+  *_at                 the same sums at listed output indices only
   explicit_A           the matrix A_n^h of Eq. 1 built by the block recursion
                        of Property 1 (S1, S5, S10), independent of conv_full
   objective            f = 1/2||A X - Y||^2 (+ lam/2 ||X||^2), section
@@ -50,7 +51,7 @@ def _load():
             f.restype = ctypes.c_int
         lib.ora_conv_adjoint_literal.argtypes = [ctypes.c_int, i64p, i64p, dp, dp, dp, dp]
         lib.ora_conv_adjoint_literal.restype = ctypes.c_int
-        for name in ("ora_conv_full_at", "ora_conv_adjoint_at"):
+        for name in ("ora_conv_full_at", "ora_conv_adjoint_at", "ora_conv_dH_at"):
             f = getattr(lib, name)
             f.argtypes = [ctypes.c_int, i64p, i64p, dp, dp, i64p, ctypes.c_int64, dp]
             f.restype = ctypes.c_int
@@ -188,6 +189,20 @@ def conv_adjoint_at(r, h, flat_idx):
                                      _ptr(r), _ptr(h), _ptr(idx, ctypes.c_int64), idx.size, _ptr(out))
     if rc:
         raise ValueError("ora_conv_adjoint_at failed (%d)" % rc)
+    return out
+
+
+def conv_dH_at(x, r, psf_shape, flat_idx):
+    """conv_dH evaluated only at the given flat PSF-shaped indices."""
+    x, r = _d(x), _d(r)
+    p = [(e - 1) // 2 for e in psf_shape]
+    m, pp = _mp(x.shape, p)
+    idx = np.ascontiguousarray(flat_idx, dtype=np.int64)
+    out = np.empty(idx.size, dtype=np.float64)
+    rc = _load().ora_conv_dH_at(x.ndim, _ptr(m, ctypes.c_int64), _ptr(pp, ctypes.c_int64),
+                                _ptr(x), _ptr(r), _ptr(idx, ctypes.c_int64), idx.size, _ptr(out))
+    if rc:
+        raise ValueError("ora_conv_dH_at failed (%d)" % rc)
     return out
 
 

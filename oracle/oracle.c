@@ -275,3 +275,37 @@ int ora_threads(void) {
   return 1;
 #endif
 }
+
+/* dH evaluated only at the flat PSF-shaped indices idx[0..cnt). */
+int ora_conv_dH_at(int n, const int64_t *m, const int64_t *p, const double *X, const double *R,
+                   const int64_t *idx, int64_t cnt, double *out) {
+  if (ora_check(n, m, p) || !X || !R || (cnt > 0 && (!idx || !out))) return -1;
+  int64_t eh[ORA_MAXN], er[ORA_MAXN];
+  for (int i = 0; i < n; ++i) {
+    eh[i] = 2 * p[i] + 1;
+    er[i] = m[i] + 2 * p[i];
+  }
+  int64_t nh = ora_prod(n, eh);
+  for (int64_t q = 0; q < cnt; ++q)
+    if (idx[q] < 0 || idx[q] >= nh) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < cnt; ++q) {
+    int64_t j[ORA_MAXN], k[ORA_MAXN], t[ORA_MAXN];
+    ora_unflat(n, idx[q], eh, j);
+    for (int i = 0; i < n; ++i) k[i] = 0;
+    double acc = 0.0;
+    for (;;) {
+      for (int i = 0; i < n; ++i) t[i] = k[i] + j[i];
+      acc += X[ora_flat(n, k, m)] * R[ora_flat(n, t, er)];
+      int i = n - 1;
+      while (i >= 0) {
+        if (++k[i] < m[i]) break;
+        k[i] = 0;
+        --i;
+      }
+      if (i < 0) break;
+    }
+    out[q] = acc;
+  }
+  return 0;
+}

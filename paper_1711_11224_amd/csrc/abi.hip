@@ -14,6 +14,10 @@ size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int 
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
                double lambda, int dtype, int precision, void *ws, double *stats, int *info, hipStream_t s);
 bool mfma_supported(const Geom &g, int dtype, int precision);
+bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype);
+size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype);
+hipError_t launch_dh(const int64_t m3[3], const int64_t p3[3], int dtype, const void *X, const void *G, void *dH,
+                     void *ws, hipStream_t s);
 ConvPlan plan_conv_mfma(const Geom &g, int dtype, int precision);
 hipError_t launch_conv_mfma(const ConvPlan &pl, const Geom &g, int dtype, int precision, const void *in,
                             const void *H, void *out, const Epi &ep, hipStream_t s);
@@ -235,6 +239,7 @@ static void dH_split(const int64_t m3[3], const int64_t p3[3], Geom &g, int &ksp
 size_t conv_dH_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype) {
   Extents E;
   if (prepare(n, m, p, dtype, NDC_PREC_NATIVE, E)) return 0;
+  if (dh_supported(E.m3, E.p3, dtype)) return dh_workspace_bytes(E.m3, E.p3, dtype);
   Geom g;
   int ks, zc;
   dH_split(E.m3, E.p3, g, ks, zc);
@@ -251,7 +256,8 @@ int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const v
   Geom g;
   int ks, zc;
   dH_split(E.m3, E.p3, g, ks, zc);
-  const size_t need = ks > 1 ? (size_t)ks * E.nh * es : 0;
+  const bool dedicated = dh_supported(E.m3, E.p3, dtype);
+  const size_t need = dedicated ? dh_workspace_bytes(E.m3, E.p3, dtype) : (ks > 1 ? (size_t)ks * E.nh * es : 0);
   if (need && (!ws || ws_bytes < need)) return NDC_EWORKSPACE;
   if (overlap(dH, E.nh * es, X, E.nx * es) || overlap(dH, E.nh * es, G, E.ny * es)) return NDC_EALIAS;
   if (need && (overlap(ws, need, X, E.nx * es) || overlap(ws, need, G, E.ny * es) || overlap(ws, need, dH, E.nh * es)))
@@ -260,6 +266,7 @@ int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const v
   Epi ep{};
   ep.mode = EPI_STORE;
   hipStream_t s = (hipStream_t)stream;
+  if (dedicated) return launch_dh(E.m3, E.p3, dtype, X, G, dH, ws, s) == hipSuccess ? NDC_OK : NDC_EDEVICE;
   if (ks == 1) {
     if (launch_conv_valu(g, dtype, NDC_PREC_NATIVE, G, X, dH, ep, 1, g.kz, s) != hipSuccess) return NDC_EDEVICE;
     return NDC_OK;

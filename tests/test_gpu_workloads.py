@@ -1,0 +1,169 @@
+"""Parity at the workload sizes, in the launch configuration the benchmark
+times: the 3-D FP32 workload (X 64x128x128, PSF 31x15x15) in full, the
+metric workload (X 128x512x512, PSF 63x31x31) on sampled outputs the oracle
+computes one by one, for every precision, and the deconvolution trajectory
+against the oracle's stored one."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.conftest import ROOT
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16": 1e-2, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def nd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1711_11224_amd as m
+    return m
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def c2(nd):
+    cfg = synth.CONFIGS["c2_3d_f32"]
+    x = synth.make_objects(cfg).astype(np.float32)
+    h = synth.psf_for(cfg).astype(np.float32)
+    yo = oracle.conv_full(x, h)
+    r = np.random.default_rng(1).standard_normal(yo.shape).astype(np.float32)
+    go = oracle.conv_adjoint(r, h)
+    return cfg, x, h, yo, r, go
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "split_bf16"])
+def test_c2_full_outputs(nd, c2, prec):
+    cfg, x, h, yo, r, go = c2
+    say("case c2 full %s" % prec)
+    dev = lambda a: torch.from_numpy(a).cuda()
+    y = nd.conv_full_nd(dev(x), dev(h), precision=prec).cpu().numpy()
+    assert y.shape == yo.shape == (94, 142, 142)
+    assert rel_l2(y, yo) <= TOL[prec]
+    g = nd.conv_adjoint_nd(dev(r), dev(h), precision=prec).cpu().numpy()
+    assert g.shape == cfg.shape
+    assert rel_l2(g, go) <= TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def c3(nd):
+    cfg = synth.CONFIGS["c3_metric"]
+    x = synth.make_objects(cfg).astype(np.float32)
+    h = synth.psf_for(cfg).astype(np.float32)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal([a + b - 1 for a, b in zip(cfg.shape, cfg.psf_shape)]).astype(np.float32)
+    iy = rng.choice(r.size, 2048, replace=False)
+    ix = rng.choice(x.size, 2048, replace=False)
+    yo = oracle.conv_full_at(x, h, iy)
+    go = oracle.conv_adjoint_at(r, h, ix)
+    return cfg, x, h, r, iy, ix, yo, go
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "split_bf16"])
+def test_c3_sampled_outputs(nd, c3, prec):
+    cfg, x, h, r, iy, ix, yo, go = c3
+    say("case c3 sampled %s" % prec)
+    xt, ht, rt = torch.from_numpy(x).cuda(), torch.from_numpy(h).cuda(), torch.from_numpy(r).cuda()
+    y = nd.conv_full_nd(xt, ht, precision=prec)
+    assert tuple(y.shape) == (190, 542, 542)
+    assert rel_l2(y.view(-1)[torch.from_numpy(iy).cuda()].cpu().numpy(), yo) <= TOL[prec]
+    del y
+    g = nd.conv_adjoint_nd(rt, ht, precision=prec)
+    assert tuple(g.shape) == (128, 512, 512)
+    assert rel_l2(g.view(-1)[torch.from_numpy(ix).cuda()].cpu().numpy(), go) <= TOL[prec]
+
+
+def test_c3_forward_edges_exact_subvolume(nd, c3):
+    """A corner sub-volume of the metric forward (every clipped boundary
+    tile type) against the oracle evaluated at each of its voxels."""
+    cfg, x, h, r, *_ = c3
+    say("case c3 corner")
+    y = nd.conv_full_nd(torch.from_numpy(x).cuda(), torch.from_numpy(h).cuda()).cpu().numpy()
+    zz, yy, xx = np.meshgrid(np.r_[0:3, 188:190], np.r_[0:3, 539:542], np.r_[0:5, 537:542], indexing="ij")
+    idx = np.ravel_multi_index((zz.ravel(), yy.ravel(), xx.ravel()), y.shape)
+    assert rel_l2(y.ravel()[idx], oracle.conv_full_at(x, h, idx)) <= 1e-5
+
+
+def _c2_inputs():
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_c2_trajectory as mk
+    return mk.inputs(), mk.sha
+
+
+def test_c2_deconv_100_iterations_vs_oracle_trajectory(nd):
+    """100 projected-gradient steps on the 3-D FP32 workload against the FP64
+    oracle's stored trajectory: same number of accepted steps and the same
+    step sizes; f_k within 1e-5 relative; X on 4096 sampled voxels within
+    1e-4 relative L2 (FP32 rounding accumulated over 100 steps)."""
+    path = os.path.join(ROOT, "tests", "golden", "c2_deconv_trajectory.json")
+    if not os.path.exists(path):
+        pytest.skip("trajectory not generated")
+    gold = json.load(open(path))
+    say("case c2 deconv 100")
+    (cfg, y, h, x0), sha = _c2_inputs()
+    assert sha(y) == gold["y_sha256"] and sha(x0) == gold["x0_sha256"] and sha(h) == gold["h_sha256"]
+    xg, st, info = nd.deconv_iterate(torch.from_numpy(y).cuda(), torch.from_numpy(h).cuda(),
+                                     torch.from_numpy(x0).cuda(), cfg.iters)
+    torch.cuda.synchronize()
+    done, status = info.cpu().tolist()
+    assert done == gold["done"] and status == gold["status"]
+    st = st.cpu().numpy()
+    np.testing.assert_array_equal(st[1:done + 1, 2], np.array(gold["rejections"]))
+    np.testing.assert_allclose(st[1:done + 1, 1], np.array(gold["delta"]), rtol=1e-14)
+    f = np.array(gold["f"])
+    assert np.max(np.abs(st[:done + 1, 0] - f) / np.abs(f)) <= 1e-5
+    xs = xg.cpu().numpy().ravel()[np.array(gold["sample_idx"])]
+    assert rel_l2(xs, np.array(gold["x_samples"])) <= 1e-4
+    assert np.all(np.diff(st[:done + 1, 0]) < 0)
+
+
+# Tolerance on f(X^0) = 1/2||A X^0 - Y||^2 for the flat start: the operator's
+# relative error e enters R = A X^0 - Y amplified by ||A X^0|| / ||R|| (about
+# 2.5 for these inputs) and f doubles it, so 5e for each precision.
+F0_TOL = {"fp32": 5e-5, "bf16": 5e-2, "split_bf16": 5e-4}
+
+
+@pytest.fixture(scope="module")
+def c3_deconv_inputs(nd):
+    cfg = synth.CONFIGS["c3_metric"]
+    rng = np.random.default_rng(5)
+    factors = synth.gaussian_factors(cfg.psf_shape, cfg.sigmas)
+    h = synth.psf_for(cfg).astype(np.float32)
+    y = rng.poisson(50.0, size=[a + b - 1 for a, b in zip(cfg.shape, cfg.psf_shape)]).astype(np.float32)
+    x0 = synth.flat_start(y, h, cfg.shape).astype(np.float32)
+    ax0 = oracle.conv_full_separable(np.full(cfg.shape, float(x0.ravel()[0])), factors)
+    f0 = 0.5 * float(np.sum((ax0 - y.astype(np.float64)) ** 2))
+    return cfg, h, y, x0, f0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "split_bf16"])
+def test_c3_deconv_steps_properties(nd, c3_deconv_inputs, prec):
+    """Metric workload, a few steps in each precision: every step accepted,
+    f strictly decreasing, X >= 0, and f(X^0) against the oracle (flat X^0
+    with the separable Gaussian PSF, one 1-D full convolution per axis)."""
+    cfg, h, y, x0, f0 = c3_deconv_inputs
+    say("case c3 deconv %s" % prec)
+    xg, st, info = nd.deconv_iterate(torch.from_numpy(y).cuda(), torch.from_numpy(h).cuda(),
+                                     torch.from_numpy(x0).cuda(), 3, precision=prec)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [3, 0]
+    f = st.cpu().numpy()[:, 0]
+    assert np.all(np.diff(f) < 0)
+    assert float(xg.min()) >= 0.0
+    assert abs(f[0] - f0) <= F0_TOL[prec] * f0

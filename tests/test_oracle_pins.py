@@ -207,6 +207,9 @@ def test_at_functions_match_dense():
     g = oracle.conv_adjoint(y, h)
     idx = RNG.choice(g.size, 40, replace=False)
     np.testing.assert_array_equal(oracle.conv_adjoint_at(y, h, idx), g.ravel()[idx])
+    dh = oracle.conv_dH(x, y, h.shape)
+    idx = RNG.choice(dh.size, 20, replace=False)
+    np.testing.assert_array_equal(oracle.conv_dH_at(x, y, h.shape, idx), dh.ravel()[idx])
 
 
 # ---------------------------------------------------------------- gradient in H
