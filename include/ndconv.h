@@ -117,6 +117,42 @@ NDC_API int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void
                    int iters, double lambda, int dtype, int precision, void *ws, size_t ws_bytes,
                    double *stats, int *info, void *stream);
 
+/* Batched form: many independent 3-D volumes, each with its own extents m,
+ * half-widths p and PSF, in persistent launches that walk one tile list for
+ * the whole batch.  Every volume keeps its own step size and acceptance
+ * decisions (the rule of deconv_iterate); one step of the whole batch is
+ * captured once into a hipGraph and replayed per step.  FP32 only; every
+ * PSF needs 3 <= 2p_x+1 <= 33 and 2p_y+1 <= 33.
+ *
+ *  ndc_batch_plan_create: m and p are count x 3 host arrays (z, y, x);
+ *    tuning is NULL or 4 ints {output planes per tile (2 or 4), work-groups
+ *    per CU (1 or 2), tile order (0 by volume, 1 interleaved, 2 costliest
+ *    volume first), use the hipGraph (0 or 1)}.  The plan owns small device
+ *    tables; destroy it with ndc_batch_plan_destroy.
+ *  ndc_batch_conv_full / ndc_batch_conv_adjoint: the two operators of every
+ *    volume in one persistent launch; the pointer arguments are host arrays
+ *    of count device pointers.  They wait for the launch to finish.
+ *  ndc_batch_deconv: `iters` accepted steps on every volume, X[v] updated in
+ *    place; ws holds ndc_batch_workspace_bytes(); stats is NULL or a host
+ *    array of count nullable device pointers (each 4*(iters+1) doubles, as in
+ *    deconv_iterate); info is NULL or a device array of 2*count ints
+ *    (iters_done, status) per volume.  Complete when it returns.
+ *  ndc_batch_plan_info: (forward tiles, transpose tiles, persistent grid,
+ *    LDS bytes per work-group). */
+typedef struct ndc_batch_plan ndc_batch_plan;
+NDC_API int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dtype, int precision,
+                                  const int *tuning, ndc_batch_plan **plan);
+NDC_API void ndc_batch_plan_destroy(ndc_batch_plan *plan);
+NDC_API size_t ndc_batch_workspace_bytes(const ndc_batch_plan *plan);
+NDC_API int ndc_batch_plan_info(const ndc_batch_plan *plan, int64_t *out4);
+NDC_API int ndc_batch_conv_full(ndc_batch_plan *plan, const void *const *X, const void *const *H, void *const *Y,
+                                void *stream);
+NDC_API int ndc_batch_conv_adjoint(ndc_batch_plan *plan, const void *const *R, const void *const *H,
+                                   void *const *X, void *stream);
+NDC_API int ndc_batch_deconv(ndc_batch_plan *plan, const void *const *Y, const void *const *H, void *const *X,
+                             int iters, double lambda, void *ws, size_t ws_bytes, double *const *stats, int *info,
+                             void *stream);
+
 /* Static text for a status code (never NULL). */
 NDC_API const char *ndc_strerror(int status);
 

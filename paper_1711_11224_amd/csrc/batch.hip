@@ -1,0 +1,520 @@
+// Batched form: many independent volumes, each with its own extents, PSF,
+// step size and line search, through persistent launches (conv_batch.hip).
+// One deconvolution step for the whole batch is a fixed sequence
+//   transpose+update (persistent) -> retry update -> forward+residual
+//   (persistent) -> per-volume decide -> per-volume commit
+// captured once into a hipGraph and replayed once per step.  Every kernel
+// reads the per-volume phase word and skips volumes with nothing to do.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ndc_device.h"
+#include "ndc_internal.h"
+
+using namespace ndc;
+
+namespace {
+
+constexpr int BT = 256;  // threads of the per-volume kernels
+constexpr int EB = 64;   // work-groups per volume in elementwise kernels
+
+inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+__device__ double bwg_sum(const double *part, int lo, int hi, int comp, double (*red)[2]) {
+  double s = 0.0, dummy = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += BT) s += part[2 * (int64_t)i + comp];
+  block_sum2(s, dummy, red);
+  __syncthreads();
+  return s;
+}
+
+// grid = count: delta_0 and the state of each volume
+__global__ __launch_bounds__(BT) void b_init_kernel(const BVol *vols, double lambda, int iters, int jmax) {
+  __shared__ double red[BT / 64][2];
+  const BVol &v = vols[blockIdx.x];
+  const int64_t nh = (int64_t)(2 * v.p[0] + 1) * (2 * v.p[1] + 1) * (2 * v.p[2] + 1);
+  double s = 0.0, dummy = 0.0;
+  for (int64_t i = threadIdx.x; i < nh; i += BT) s += fabs((double)v.H[i]);
+  block_sum2(s, dummy, red);
+  if (threadIdx.x == 0) {
+    DState *st = v.st;
+    st->delta0 = 1.0 / (s * s + lambda);
+    st->delta = st->delta0;
+    st->lambda = lambda;
+    st->f_cur = 0.0;
+    st->phase = PH_NEW;
+    st->k = 0;
+    st->rej = 0;
+    st->status = 0;
+    st->iters = iters;
+    st->jmax = jmax;
+    st->accepted = 0;
+  }
+}
+
+// grid = count * EB: ||X||^2 partials of each volume
+__global__ __launch_bounds__(BT) void b_sumsq_kernel(const BVol *vols, double *part_ew) {
+  __shared__ double red[BT / 64][2];
+  const int vi = blockIdx.x / EB, bi = blockIdx.x % EB;
+  const BVol &v = vols[vi];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = bi * (int64_t)BT + threadIdx.x; i < v.n; i += (int64_t)EB * BT) {
+    const double x = (double)v.X[i];
+    s0 += x * x;
+  }
+  block_sum2(s0, s1, red);
+  if (threadIdx.x == 0) {
+    part_ew[2 * (int64_t)blockIdx.x] = s0;
+    part_ew[2 * (int64_t)blockIdx.x + 1] = 0.0;
+  }
+}
+
+// grid = count: f(X^0)
+__global__ __launch_bounds__(BT) void b_f0_kernel(const BVol *vols, const double *part_fwd, const double *part_ew) {
+  __shared__ double red[BT / 64][2];
+  const int vi = blockIdx.x;
+  const BVol &v = vols[vi];
+  const double r2 = bwg_sum(part_fwd, v.fwd_lo, v.fwd_hi, 0, red);
+  const double x2 = bwg_sum(part_ew, vi * EB, vi * EB + EB, 0, red);
+  if (threadIdx.x == 0) {
+    DState *st = v.st;
+    const double f0 = 0.5 * r2 + 0.5 * st->lambda * x2;
+    st->f_cur = f0;
+    if (!isfinite(f0)) {
+      st->status = NDC_ENONFINITE;
+      st->phase = PH_DONE;
+    } else {
+      st->phase = st->iters > 0 ? PH_NEW : PH_DONE;
+    }
+    if (v.stats) {
+      v.stats[0] = f0;
+      v.stats[1] = NAN;
+      v.stats[2] = 0.0;
+      v.stats[3] = NAN;
+    }
+    if (v.info) {
+      v.info[0] = 0;
+      v.info[1] = st->status;
+    }
+  }
+}
+
+// grid = count * EB: retry with the halved step (phase RETRY only)
+__global__ __launch_bounds__(BT) void b_update_kernel(const BVol *vols, double *part_ew) {
+  const int vi = blockIdx.x / EB, bi = blockIdx.x % EB;
+  const BVol &v = vols[vi];
+  if (v.st->phase != PH_RETRY) return;
+  __shared__ double red[BT / 64][2];
+  const float d = (float)v.st->delta;
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = bi * (int64_t)BT + threadIdx.x; i < v.n; i += (int64_t)EB * BT) {
+    const float x = v.X[i];
+    const float xt = proj_nonneg<float>(x - d * v.G[i]);
+    v.Xt[i] = xt;
+    s0 += (double)xt * (double)xt;
+    const double dd = (double)xt - (double)x;
+    s1 += dd * dd;
+  }
+  block_sum2(s0, s1, red);
+  if (threadIdx.x == 0) {
+    part_ew[2 * (int64_t)blockIdx.x] = s0;
+    part_ew[2 * (int64_t)blockIdx.x + 1] = s1;
+  }
+}
+
+// grid = count: the acceptance rule f(X_t) < f(X^k) per volume
+__global__ __launch_bounds__(BT) void b_decide_kernel(const BVol *vols, const double *part_fwd,
+                                                      const double *part_adj, const double *part_ew) {
+  const int vi = blockIdx.x;
+  const BVol &v = vols[vi];
+  DState *st = v.st;
+  const int phase = st->phase;
+  if (phase == PH_DONE) {
+    if (threadIdx.x == 0) st->accepted = 0;
+    return;
+  }
+  __shared__ double red[BT / 64][2];
+  const double r2 = bwg_sum(part_fwd, v.fwd_lo, v.fwd_hi, 0, red);
+  const double *pu = phase == PH_NEW ? part_adj : part_ew;
+  const int lo = phase == PH_NEW ? v.adj_lo : vi * EB, hi = phase == PH_NEW ? v.adj_hi : vi * EB + EB;
+  const double x2 = bwg_sum(pu, lo, hi, 0, red);
+  const double dx2 = bwg_sum(pu, lo, hi, 1, red);
+  if (threadIdx.x != 0) return;
+  const double ft = 0.5 * r2 + 0.5 * st->lambda * x2;
+  if (!isfinite(ft)) {
+    st->status = NDC_ENONFINITE;
+    st->phase = PH_DONE;
+    st->accepted = 0;
+  } else if (ft < st->f_cur) {
+    const int k = st->k + 1;
+    if (v.stats) {
+      v.stats[4 * k + 0] = ft;
+      v.stats[4 * k + 1] = st->delta;
+      v.stats[4 * k + 2] = (double)st->rej;
+      v.stats[4 * k + 3] = sqrt(dx2);
+    }
+    st->k = k;
+    st->f_cur = ft;
+    st->rej = 0;
+    st->delta = st->delta0;
+    st->accepted = 1;
+    st->phase = k >= st->iters ? PH_DONE : PH_NEW;
+  } else {
+    st->accepted = 0;
+    st->rej += 1;
+    st->delta *= 0.5;
+    if (st->rej >= st->jmax) {
+      st->status = 1;
+      st->phase = PH_DONE;
+    } else {
+      st->phase = PH_RETRY;
+    }
+  }
+  if (v.info) {
+    v.info[0] = st->k;
+    v.info[1] = st->status;
+  }
+}
+
+// grid = count * EB: X <- X_t, R <- R_t right after an acceptance
+__global__ __launch_bounds__(BT) void b_commit_kernel(const BVol *vols) {
+  const int vi = blockIdx.x / EB, bi = blockIdx.x % EB;
+  const BVol &v = vols[vi];
+  if (!v.st->accepted) return;
+  const int64_t m = v.n > v.ny ? v.n : v.ny;
+  for (int64_t i = bi * (int64_t)BT + threadIdx.x; i < m; i += (int64_t)EB * BT) {
+    if (i < v.n) v.X[i] = v.Xt[i];
+    if (i < v.ny) v.R[i] = v.Rt[i];
+  }
+}
+
+}  // namespace
+
+struct ndc_batch_plan {
+  int count = 0, mg = 4, wg_per_cu = 2, order = 0, use_graph = 1;
+  std::vector<int64_t> m, p;  // count x 3
+  std::vector<BTile> fwd, adj;
+  BTile *d_fwd = nullptr, *d_adj = nullptr;
+  BVol *d_vols = nullptr;       // deconvolution table
+  BVol *d_vols_conv = nullptr;  // convolution-only table
+  std::vector<BVol> h_vols, h_vols_conv;
+  size_t lds_fwd = 0, lds_adj = 0;
+  int grid = 512;
+  // workspace layout
+  std::vector<size_t> off_xt, off_g, off_r, off_rt;
+  size_t off_state = 0, off_pf = 0, off_pa = 0, off_pe = 0, ws_total = 0;
+  // captured step
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void *exec_ws = nullptr;
+};
+
+namespace {
+
+void make_tiles(ndc_batch_plan *P, bool forward, std::vector<BTile> &out, std::vector<int> &lo,
+                std::vector<int> &hi) {
+  std::vector<std::vector<BTile>> per(P->count);
+  int slot = 0;
+  lo.assign(P->count, 0);
+  hi.assign(P->count, 0);
+  for (int v = 0; v < P->count; ++v) {
+    const int64_t *m = &P->m[3 * v], *p = &P->p[3 * v];
+    const int oz = (int)(forward ? m[0] + 2 * p[0] : m[0]);
+    const int oy = (int)(forward ? m[1] + 2 * p[1] : m[1]);
+    const int ox = (int)(forward ? m[2] + 2 * p[2] : m[2]);
+    const dim3 t = batch_tile_counts(oz, oy, ox, P->mg);
+    lo[v] = slot;
+    for (unsigned tz = 0; tz < t.z; ++tz)
+      for (unsigned ty = 0; ty < t.y; ++ty)
+        for (unsigned tx = 0; tx < t.x; ++tx) {
+          BTile b{};
+          b.vol = v;
+          b.tx = (int)tx;
+          b.ty = (int)ty;
+          b.tz = (int)tz;
+          b.slot = slot++;
+          per[v].push_back(b);
+        }
+    hi[v] = slot;
+  }
+  out.clear();
+  if (P->order == 1) {  // interleave volumes tile by tile
+    size_t most = 0;
+    for (auto &q : per) most = std::max(most, q.size());
+    for (size_t i = 0; i < most; ++i)
+      for (auto &q : per)
+        if (i < q.size()) out.push_back(q[i]);
+  } else if (P->order == 2) {  // most expensive volumes first (PSF taps x tiles)
+    std::vector<int> idx(P->count);
+    for (int v = 0; v < P->count; ++v) idx[v] = v;
+    auto cost = [&](int v) {
+      const int64_t *p = &P->p[3 * v];
+      return (double)(2 * p[0] + 1) * (2 * p[1] + 1) * (2 * p[2] + 4) * per[v].size();
+    };
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    for (int v : idx) out.insert(out.end(), per[v].begin(), per[v].end());
+  } else {
+    for (auto &q : per) out.insert(out.end(), q.begin(), q.end());
+  }
+}
+
+int to_device(const void *h, size_t n, void **d) {
+  if (hipMalloc(d, n ? n : 1) != hipSuccess) return NDC_EDEVICE;
+  if (n && hipMemcpy(*d, h, n, hipMemcpyHostToDevice) != hipSuccess) return NDC_EDEVICE;
+  return NDC_OK;
+}
+
+hipError_t launch_step(ndc_batch_plan *P, char *ws, hipStream_t s) {
+  double *pf = (double *)(ws + P->off_pf), *pa = (double *)(ws + P->off_pa), *pe = (double *)(ws + P->off_pe);
+  hipError_t e;
+  e = launch_batch_conv(P->mg, P->d_vols, P->d_adj, (int)P->adj.size(), BOP_STEP_ADJ, pa, P->grid, P->lds_adj, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(b_update_kernel, dim3(P->count * EB), dim3(BT), 0, s, (const BVol *)P->d_vols, pe);
+  e = launch_batch_conv(P->mg, P->d_vols, P->d_fwd, (int)P->fwd.size(), BOP_STEP_FWD, pf, P->grid, P->lds_fwd, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(b_decide_kernel, dim3(P->count), dim3(BT), 0, s, (const BVol *)P->d_vols, (const double *)pf,
+                     (const double *)pa, (const double *)pe);
+  hipLaunchKernelGGL(b_commit_kernel, dim3(P->count * EB), dim3(BT), 0, s, (const BVol *)P->d_vols);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dtype, int precision, const int *tuning,
+                          ndc_batch_plan **out) {
+  if (!out) return NDC_EINVAL;
+  *out = nullptr;
+  if (count < 1 || !m || !p) return NDC_EINVAL;
+  if (dtype != NDC_F32 && dtype != NDC_F64) return NDC_EINVAL;
+  if (precision < NDC_PREC_NATIVE || precision > NDC_PREC_SPLIT_BF16) return NDC_EINVAL;
+  if (dtype != NDC_F32 || precision != NDC_PREC_NATIVE) return NDC_EUNSUPPORTED;
+  for (int v = 0; v < count; ++v)
+    for (int i = 0; i < 3; ++i) {
+      if (m[3 * v + i] < 1 || p[3 * v + i] < 0) return NDC_EINVAL;
+      if (m[3 * v + i] + 4 * p[3 * v + i] > (1 << 20)) return NDC_EUNSUPPORTED;
+    }
+  for (int v = 0; v < count; ++v)
+    if (!batch_psf_supported((int)(2 * p[3 * v + 2] + 1), (int)(2 * p[3 * v + 1] + 1))) return NDC_EUNSUPPORTED;
+  int mg = 4, wpc = 2, order = 0, graph = 1;
+  if (tuning) {
+    mg = tuning[0];
+    wpc = tuning[1];
+    order = tuning[2];
+    graph = tuning[3];
+    if ((mg != 2 && mg != 4) || wpc < 1 || wpc > 2 || order < 0 || order > 2 || graph < 0 || graph > 1)
+      return NDC_EINVAL;
+  }
+  ndc_batch_plan *P = new ndc_batch_plan();
+  P->count = count;
+  P->mg = mg;
+  P->wg_per_cu = wpc;
+  P->order = order;
+  P->use_graph = graph;
+  P->m.assign(m, m + 3 * count);
+  P->p.assign(p, p + 3 * count);
+  std::vector<int> flo, fhi, alo, ahi;
+  make_tiles(P, true, P->fwd, flo, fhi);
+  make_tiles(P, false, P->adj, alo, ahi);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete P;
+    return NDC_EDEVICE;
+  }
+  P->grid = cus * wpc;
+  // workspace layout and the volume tables
+  size_t o = 0;
+  P->off_state = o;
+  o += al256(sizeof(DState) * count);
+  P->off_pf = o;
+  o += al256(sizeof(double) * 2 * P->fwd.size());
+  P->off_pa = o;
+  o += al256(sizeof(double) * 2 * P->adj.size());
+  P->off_pe = o;
+  o += al256(sizeof(double) * 2 * (size_t)count * EB);
+  P->h_vols.resize(count);
+  P->h_vols_conv.resize(count);
+  for (int v = 0; v < count; ++v) {
+    BVol &b = P->h_vols[v];
+    memset(&b, 0, sizeof(b));
+    int64_t n = 1, ny = 1;
+    for (int i = 0; i < 3; ++i) {
+      b.m[i] = (int)m[3 * v + i];
+      b.p[i] = (int)p[3 * v + i];
+      n *= m[3 * v + i];
+      ny *= m[3 * v + i] + 2 * p[3 * v + i];
+    }
+    b.n = n;
+    b.ny = ny;
+    b.fwd_lo = flo[v];
+    b.fwd_hi = fhi[v];
+    b.adj_lo = alo[v];
+    b.adj_hi = ahi[v];
+    P->off_xt.push_back(o);
+    o += al256(sizeof(float) * n);
+    P->off_g.push_back(o);
+    o += al256(sizeof(float) * n);
+    P->off_r.push_back(o);
+    o += al256(sizeof(float) * ny);
+    P->off_rt.push_back(o);
+    o += al256(sizeof(float) * ny);
+    const size_t lf = batch_lds_bytes(2 * b.p[2] + 1, 2 * b.p[1] + 1, mg);
+    P->lds_fwd = std::max(P->lds_fwd, lf);
+    P->lds_adj = std::max(P->lds_adj, lf);
+    P->h_vols_conv[v] = b;
+  }
+  P->ws_total = o;
+  int rc = to_device(P->fwd.data(), sizeof(BTile) * P->fwd.size(), (void **)&P->d_fwd);
+  if (!rc) rc = to_device(P->adj.data(), sizeof(BTile) * P->adj.size(), (void **)&P->d_adj);
+  if (!rc) rc = to_device(P->h_vols.data(), sizeof(BVol) * count, (void **)&P->d_vols);
+  if (!rc) rc = to_device(P->h_vols_conv.data(), sizeof(BVol) * count, (void **)&P->d_vols_conv);
+  if (!rc && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) rc = NDC_EDEVICE;
+  if (rc) {
+    ndc_batch_plan_destroy(P);
+    return rc;
+  }
+  *out = P;
+  return NDC_OK;
+}
+
+void ndc_batch_plan_destroy(ndc_batch_plan *P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
+  (void)hipFree(P->d_fwd);
+  (void)hipFree(P->d_adj);
+  (void)hipFree(P->d_vols);
+  (void)hipFree(P->d_vols_conv);
+  (void)hipGetLastError();
+  delete P;
+}
+
+size_t ndc_batch_workspace_bytes(const ndc_batch_plan *P) { return P ? P->ws_total : 0; }
+
+int ndc_batch_plan_info(const ndc_batch_plan *P, int64_t *out4) {
+  if (!P || !out4) return NDC_EINVAL;
+  out4[0] = (int64_t)P->fwd.size();
+  out4[1] = (int64_t)P->adj.size();
+  out4[2] = P->grid;
+  out4[3] = (int64_t)std::max(P->lds_fwd, P->lds_adj);
+  return NDC_OK;
+}
+
+static int batch_conv(ndc_batch_plan *P, const void *const *in, const void *const *H, void *const *out, bool forward,
+                      void *stream) {
+  if (!P || !in || !H || !out) return NDC_EINVAL;
+  for (int v = 0; v < P->count; ++v) {
+    if (!in[v] || !H[v] || !out[v]) return NDC_EINVAL;
+    BVol &b = P->h_vols_conv[v];
+    const size_t nin = sizeof(float) * (forward ? b.n : b.ny), nout = sizeof(float) * (forward ? b.ny : b.n);
+    const size_t nh = sizeof(float) * (2 * b.p[0] + 1) * (2 * b.p[1] + 1) * (2 * b.p[2] + 1);
+    const uintptr_t o = (uintptr_t)out[v];
+    auto ov = [&](const void *q, size_t nq) { return o < (uintptr_t)q + nq && (uintptr_t)q < o + nout; };
+    if (ov(in[v], nin) || ov(H[v], nh)) return NDC_EALIAS;
+    b.H = (const float *)H[v];
+    b.X = forward ? (float *)in[v] : (float *)out[v];
+    b.R = forward ? (float *)out[v] : (float *)in[v];
+    b.st = nullptr;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(P->d_vols_conv, P->h_vols_conv.data(), sizeof(BVol) * P->count, hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return NDC_EDEVICE;
+  hipError_t e = forward ? launch_batch_conv(P->mg, P->d_vols_conv, P->d_fwd, (int)P->fwd.size(), BOP_FWD, nullptr,
+                                             P->grid, P->lds_fwd, s)
+                         : launch_batch_conv(P->mg, P->d_vols_conv, P->d_adj, (int)P->adj.size(), BOP_ADJ, nullptr,
+                                             P->grid, P->lds_adj, s);
+  if (e != hipSuccess) return NDC_EDEVICE;
+  // the table must not change before the launch has read it
+  return hipStreamSynchronize(s) == hipSuccess ? NDC_OK : NDC_EDEVICE;
+}
+
+int ndc_batch_conv_full(ndc_batch_plan *P, const void *const *X, const void *const *H, void *const *Y, void *stream) {
+  return batch_conv(P, X, H, Y, true, stream);
+}
+
+int ndc_batch_conv_adjoint(ndc_batch_plan *P, const void *const *R, const void *const *H, void *const *X,
+                           void *stream) {
+  return batch_conv(P, R, H, X, false, stream);
+}
+
+int ndc_batch_deconv(ndc_batch_plan *P, const void *const *Y, const void *const *H, void *const *X, int iters,
+                     double lambda, void *ws, size_t ws_bytes, double *const *stats, int *info, void *stream) {
+  if (!P || !Y || !H || !X) return NDC_EINVAL;
+  if (iters < 0 || !(lambda >= 0.0) || !isfinite(lambda)) return NDC_EINVAL;
+  if (!ws || ws_bytes < P->ws_total) return NDC_EWORKSPACE;
+  char *w = (char *)ws;
+  const uintptr_t wl = (uintptr_t)ws, wh = wl + P->ws_total;
+  for (int v = 0; v < P->count; ++v) {
+    if (!Y[v] || !H[v] || !X[v]) return NDC_EINVAL;
+    BVol &b = P->h_vols[v];
+    const uintptr_t x = (uintptr_t)X[v];
+    if (x < wh && wl < x + sizeof(float) * b.n) return NDC_EALIAS;
+    b.Y = (const float *)Y[v];
+    b.H = (const float *)H[v];
+    b.X = (float *)X[v];
+    b.Xt = (float *)(w + P->off_xt[v]);
+    b.G = (float *)(w + P->off_g[v]);
+    b.R = (float *)(w + P->off_r[v]);
+    b.Rt = (float *)(w + P->off_rt[v]);
+    b.st = (DState *)(w + P->off_state) + v;
+    b.stats = stats ? stats[v] : nullptr;
+    b.info = info ? info + 2 * v : nullptr;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double *pf = (double *)(w + P->off_pf), *pe = (double *)(w + P->off_pe);
+  if (hipMemcpyAsync(P->d_vols, P->h_vols.data(), sizeof(BVol) * P->count, hipMemcpyHostToDevice, s) != hipSuccess)
+    return NDC_EDEVICE;
+  hipLaunchKernelGGL(b_init_kernel, dim3(P->count), dim3(BT), 0, s, (const BVol *)P->d_vols, lambda, iters, 30);
+  hipLaunchKernelGGL(b_sumsq_kernel, dim3(P->count * EB), dim3(BT), 0, s, (const BVol *)P->d_vols, pe);
+  if (launch_batch_conv(P->mg, P->d_vols, P->d_fwd, (int)P->fwd.size(), BOP_INIT, pf, P->grid, P->lds_fwd, s) !=
+      hipSuccess)
+    return NDC_EDEVICE;
+  hipLaunchKernelGGL(b_f0_kernel, dim3(P->count), dim3(BT), 0, s, (const BVol *)P->d_vols, (const double *)pf,
+                     (const double *)pe);
+  if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
+
+  if (P->use_graph && P->exec_ws != ws) {  // capture one step against this workspace
+    if (P->exec) {
+      (void)hipGraphExecDestroy(P->exec);
+      P->exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return NDC_EDEVICE;
+    const hipError_t le = launch_step(P, w, P->cap);
+    const hipError_t ce = hipStreamEndCapture(P->cap, &graph);
+    if (le != hipSuccess || ce != hipSuccess || !graph) return NDC_EDEVICE;
+    const hipError_t ie = hipGraphInstantiate(&P->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      P->exec = nullptr;
+      return NDC_EDEVICE;
+    }
+    P->exec_ws = ws;
+  }
+  std::vector<DState> hs(P->count);
+  int remaining = iters;
+  while (remaining > 0) {
+    for (int step = 0; step < remaining; ++step) {
+      const hipError_t e = P->use_graph ? hipGraphLaunch(P->exec, s) : launch_step(P, w, s);
+      if (e != hipSuccess) return NDC_EDEVICE;
+    }
+    if (hipMemcpyAsync(hs.data(), w + P->off_state, sizeof(DState) * P->count, hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return NDC_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return NDC_EDEVICE;
+    remaining = 0;
+    for (int v = 0; v < P->count; ++v)
+      if (hs[v].phase != PH_DONE) remaining = std::max(remaining, iters - hs[v].k);
+  }
+  // the volume table is reused by the next call: wait until this one is done
+  return hipStreamSynchronize(s) == hipSuccess ? NDC_OK : NDC_EDEVICE;
+}
+
+}  // extern "C"

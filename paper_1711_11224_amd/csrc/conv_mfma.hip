@@ -1,306 +1,37 @@
-// Matrix-core correlation kernels for PSFs wide enough along x that the
-// contraction is dense (3 <= kx <= 33, ky <= 33, any kz).
-//
-// out[s] = sum_t Hc[t] in[s + t - off]  (see Geom), FP32 storage.
-//
-// FP32: v_mfma_f32_4x4x1f32 (16 independent 4x4 blocks, K = 1).
-//   Block b, lanes 4b..4b+3.  D_b[i][j] += A_src[i] * B_b[j], D_b[i][j] in
-//   accumulator register i of lane 4b+j.  With CBSZ = 4 the A operand of
-//   every block is taken from block ABID, so one VGPR holds A for 16 steps.
-// Mapping (a Toeplitz form of one PSF row):
-//   lane 4b+j, register i  <->  output (row j, x = x0 + 4b + i)
-//   step k in [0, kx+3):  A[i] = Hc_row[k - i] (zero outside [0,kx)),
-//                         B[j] = in_row_j[x0 + 4b + k - offx]
-//   so sum_k A[i] B[j] = sum_t Hc_row[t] in_row_j[x + t - offx].
-//   Only 3 of every kx+3 steps multiply Toeplitz zeros.
-// BF16 / split-BF16: v_mfma_f32_4x4x4bf16_1k, the same mapping with four
-//   consecutive steps per instruction (A[i][k'] = Hc_row[4c + k' - i],
-//   B[k'][j] = in_row_j[x0 + 4b + 4c + k' - offx]).  Operands are rounded to
-//   bf16 (nearest even) in registers from the FP32 LDS tiles; split-BF16 adds
-//   the hi*lo and lo*hi products of v = hi + lo, lo = bf16(v - hi).
-// Work-group: 4 waves, output tile G=4 z-planes x 16 rows x 64 columns;
-// wave w owns rows 4w..4w+3 of every plane.  Input planes stream through a
-// double-buffered LDS tile; each staged plane feeds the G output planes it
-// reaches through G different PSF planes, held in an LDS ring of G+1 planes.
-// Partial sums are blocked per PSF row into FP32 accumulators.
-#include <type_traits>
-
-#include "ndc_device.h"
-#include "ndc_internal.h"
+// Single-volume launches of the matrix-core correlation tile (mfma_tile.h).
+#include "mfma_tile.h"
 
 namespace ndc {
 namespace {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
-typedef short v4s __attribute__((ext_vector_type(4)));
-
-// Compile-time loop: f(integral_constant<int, I>) for I in [B, E).
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
-constexpr int MT = 256;       // threads per work-group (4 waves)
-constexpr int MG = 4;         // output z-planes per work-group
-constexpr int MROWS = 16;     // output rows per work-group
-constexpr int MCOLS = 64;     // output columns per work-group
-constexpr int MAX_KY = 33;
-
-template <int KX>
-struct MfmaShape {
-  static constexpr int KS = KX + 3;               // unit steps per PSF row
-  static constexpr int NC = (KS + 15) / 16;       // FP32: broadcast A registers per row
-  static constexpr int NW = (KS + 3) / 4;         // float4 input windows per lane (= bf16 chunks)
-  static constexpr int NCB = (NW + 15) / 16;      // bf16: broadcast A registers per row
-  static constexpr int TCOLS = 60 + 4 * NW;       // staged input columns
-  static constexpr int STRIDE = ((TCOLS + 23) / 32) * 32 + 8;  // = 8 mod 32 floats
-  static constexpr int HS = 16 * NC + 4;          // LDS PSF row stride (>= 4*NW + 3)
-  static constexpr int NIN = ((MROWS + MAX_KY - 1) * TCOLS + MT - 1) / MT;
-  static constexpr int NH = (MAX_KY * HS + MT - 1) / MT;
-};
-
-__host__ __device__ constexpr int mfma_lds_floats(int ky, int stride, int hs) {
-  return 2 * (MROWS + ky - 1) * stride + (MG + 1) * ky * hs;
-}
-
-__device__ __forceinline__ v4s to_bf16(v4f v) { return __builtin_bit_cast(v4s, __builtin_convertvector(v, v4bf)); }
-__device__ __forceinline__ void split_bf16(v4f v, v4s &hi, v4s &lo) {
-  const v4bf h = __builtin_convertvector(v, v4bf);
-  hi = __builtin_bit_cast(v4s, h);
-  lo = to_bf16(v - __builtin_convertvector(h, v4f));
-}
+using namespace mfma;
 
 template <int KX, int PREC>
 __global__ __launch_bounds__(MT, 2) void conv_mfma_kernel(const float *__restrict__ in, const float *__restrict__ H,
                                                           float *__restrict__ out, Geom g, Epi ep, int nbx, int nby,
                                                           int nbz) {
-  using S = MfmaShape<KX>;
   if (ep.phase && !((1 << *ep.phase) & ep.phase_mask)) return;  // uniform early exit
   extern __shared__ __align__(16) float lds[];
   __shared__ double red[MT / 64][2];
-
   // Tiles in x-fastest order.  (An XCD-grouped, z-fastest order that keeps
   // tiles sharing input planes on one L2 cuts HBM fetches but ends each XCD
   // on expensive mid-volume tiles; measured 5% slower for the forward.)
   const int id = blockIdx.x;
-  const int tx = id % nbx, ty = (id / nbx) % nby, tz = id / (nbx * nby);
   (void)nbz;
-
-  const int rows = MROWS + g.ky - 1;
-  float *tile0 = lds;
-  float *tile1 = lds + rows * S::STRIDE;
-  float *ring = lds + 2 * rows * S::STRIDE;
-  const int hplane = g.ky * S::HS;
-
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
-  const int bb = lane >> 2, jj = lane & 3;                  // block, row within block (B and D)
-  const int x0 = tx * MCOLS, y0 = ty * MROWS, z0 = tz * MG;
-
-  // input planes that reach this tile, clipped to the input
-  const int r_lo = max(0, z0 - g.offz);
-  const int r_hi = min(g.iz - 1, z0 + MG - 1 + g.kz - 1 - g.offz);
-
-  // staging helpers ------------------------------------------------------------
-  float inreg[S::NIN];
-  float hreg[S::NH];
-  auto load_plane = [&](int zin) {
-#pragma unroll
-    for (int u = 0; u < S::NIN; ++u) {
-      const int e = tid + u * MT;
-      const int r = e / S::TCOLS, q = e - r * S::TCOLS;
-      const int yin = y0 + r - g.offy, xin = x0 + q - g.offx;
-      float v = 0.f;
-      if (r < rows && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix)
-        v = in[((int64_t)zin * g.iy + yin) * g.ix + xin];
-      inreg[u] = v;
-    }
-  };
-  auto store_plane = [&](float *t) {
-#pragma unroll
-    for (int u = 0; u < S::NIN; ++u) {
-      const int e = tid + u * MT;
-      const int r = e / S::TCOLS, q = e - r * S::TCOLS;
-      if (r < rows) t[r * S::STRIDE + q] = inreg[u];
-    }
-  };
-  auto load_h = [&](int a) {  // PSF plane a of Hc, rows padded with 3 leading zeros
-#pragma unroll
-    for (int u = 0; u < S::NH; ++u) {
-      const int e = tid + u * MT;
-      const int b = e / S::HS, t = e - b * S::HS - 3;
-      float v = 0.f;
-      if (b < g.ky && t >= 0 && t < KX) {
-        const int ha = g.flip ? g.kz - 1 - a : a;
-        const int hb = g.flip ? g.ky - 1 - b : b;
-        const int hc = g.flip ? KX - 1 - t : t;
-        v = H[((int64_t)ha * g.ky + hb) * KX + hc];
-      }
-      hreg[u] = v;
-    }
-  };
-  auto store_h = [&](int a) {
-    float *dst = ring + (a % (MG + 1)) * hplane;
-#pragma unroll
-    for (int u = 0; u < S::NH; ++u) {
-      const int e = tid + u * MT;
-      if (e < hplane) dst[e] = hreg[u];
-    }
-  };
-
-  v4f acc[MG];
-#pragma unroll
-  for (int q = 0; q < MG; ++q) acc[q] = (v4f){0.f, 0.f, 0.f, 0.f};
-
-  if (r_lo <= r_hi) {
-    // prologue: first input plane and the PSF planes its step needs
-    load_plane(r_lo);
-    store_plane(tile0);
-    for (int a = max(0, r_lo - z0 - MG + 1 + g.offz); a <= min(g.kz - 1, r_lo - z0 + g.offz); ++a) {
-      load_h(a);
-      store_h(a);
-    }
-    __syncthreads();
-
-    // rows of this wave's outputs that reach the input, as a tap range
-    const int b_lo = max(0, g.offy - y0 - 4 * w - 3);
-    const int b_hi = min(g.ky - 1, g.iy - 1 + g.offy - y0 - 4 * w);
-    const bool wave_live = (y0 + 4 * w < g.oy);
-
-    for (int zin = r_lo; zin <= r_hi; ++zin) {
-      const float *tile = ((zin - r_lo) & 1) ? tile1 : tile0;
-      const bool more = zin < r_hi;
-      const int a_new = zin + 1 - z0 + g.offz;
-      const bool new_h = more && a_new >= 0 && a_new < g.kz;
-      if (more) load_plane(zin + 1);
-      if (new_h) load_h(a_new);
-
-      if (wave_live) {
-        int aq[MG];
-        bool live[MG];
-#pragma unroll
-        for (int q = 0; q < MG; ++q) {
-          aq[q] = zin - z0 - q + g.offz;
-          live[q] = aq[q] >= 0 && aq[q] < g.kz && z0 + q < g.oz;
-        }
-        for (int b = b_lo; b <= b_hi; ++b) {
-          // B operand: consecutive inputs of row (4w + jj + b), column 4*bb + k
-          const float *src = tile + (4 * w + jj + b) * S::STRIDE + 4 * bb;
-          v4f win[S::NW];
-#pragma unroll
-          for (int u = 0; u < S::NW; ++u) win[u] = *(const v4f *)(src + 4 * u);
-          v4f d[MG];
-          if constexpr (PREC == PREC_NATIVE_) {
-            // A operand: lane 4s+i holds Hc_row[16c + s - i]
-            float hv[MG][S::NC];
-#pragma unroll
-            for (int q = 0; q < MG; ++q) {
-              const float *hrow = ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane + b * S::HS + 3 + bb - jj;
-#pragma unroll
-              for (int c = 0; c < S::NC; ++c) hv[q][c] = live[q] ? hrow[16 * c] : 0.f;
-            }
-            static_for<0, S::KS>([&](auto kc) {
-              constexpr int k = decltype(kc)::value;
-              const float bk = win[k >> 2][k & 3];
-              static_for<0, MG>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                const v4f c0 = k == 0 ? (v4f){0.f, 0.f, 0.f, 0.f} : d[q];
-                d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, c0, 4, k & 15, 0);
-              });
-            });
-          } else {
-            // A operand: lane 4s+i holds Hc_row[4c + k' - i], k' = 0..3, chunk c = 16r + s
-            v4s ahi[MG][S::NCB], alo[MG][S::NCB];
-#pragma unroll
-            for (int q = 0; q < MG; ++q) {
-              const float *hrow = ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane + b * S::HS + 3 - jj;
-#pragma unroll
-              for (int r = 0; r < S::NCB; ++r) {
-                const int c = 16 * r + bb;
-                v4f hv4 = (v4f){0.f, 0.f, 0.f, 0.f};
-                if (live[q] && c < S::NW) {
-                  const float *p4 = hrow + 4 * c;
-                  hv4 = (v4f){p4[0], p4[1], p4[2], p4[3]};
-                }
-                if constexpr (PREC == PREC_SPLIT_)
-                  split_bf16(hv4, ahi[q][r], alo[q][r]);
-                else
-                  ahi[q][r] = to_bf16(hv4);
-              }
-            }
-            static_for<0, S::NW>([&](auto cc) {
-              constexpr int c = decltype(cc)::value;
-              v4s bhi, blo;
-              if constexpr (PREC == PREC_SPLIT_)
-                split_bf16(win[c], bhi, blo);
-              else
-                bhi = to_bf16(win[c]);
-              static_for<0, MG>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                const v4f c0 = c == 0 ? (v4f){0.f, 0.f, 0.f, 0.f} : d[q];
-                if constexpr (PREC == PREC_SPLIT_) {
-                  v4f t = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(alo[q][c >> 4], bhi, c0, 4, c & 15, 0);
-                  t = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q][c >> 4], blo, t, 4, c & 15, 0);
-                  d[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q][c >> 4], bhi, t, 4, c & 15, 0);
-                } else {
-                  d[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q][c >> 4], bhi, c0, 4, c & 15, 0);
-                }
-              });
-            });
-          }
-#pragma unroll
-          for (int q = 0; q < MG; ++q) acc[q] += d[q];
-        }
-      }
-
-      if (more) store_plane(((zin + 1 - r_lo) & 1) ? tile1 : tile0);
-      if (new_h) store_h(a_new);
-      __syncthreads();
-    }
-  }
-
-  // Epilogue: lane (bb, jj) holds x = x0 + 4bb + i, row y0 + 4w + jj -----------
-  double s0 = 0.0, s1 = 0.0;
-  const int y = y0 + 4 * w + jj;
-  if (y < g.oy) {
-#pragma unroll
-    for (int q = 0; q < MG; ++q) {
-      const int z = z0 + q;
-      if (z < g.oz) {
-        const int64_t rowbase = ((int64_t)z * g.oy + y) * g.ox;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int x = x0 + 4 * bb + i;
-          if (x < g.ox) apply_epilogue<float>(out, rowbase + x, acc[q][i], ep, s0, s1);
-        }
-      }
-    }
-  }
-  if (ep.mode != EPI_STORE) {
-    block_sum2(s0, s1, red);
-    if (tid == 0) {
-      ep.part[2 * (int64_t)id] = s0;
-      ep.part[2 * (int64_t)id + 1] = s1;
-    }
-  }
+  mfma_tile<KX, PREC, MG_DEFAULT>(in, H, out, g, ep, id % nbx, (id / nbx) % nby, id / (nbx * nby), id, lds, red);
 }
 
 dim3 tile_counts(const Geom &g) {
-  return dim3((g.ox + MCOLS - 1) / MCOLS, (g.oy + MROWS - 1) / MROWS, (g.oz + MG - 1) / MG);
+  return dim3((g.ox + MCOLS - 1) / MCOLS, (g.oy + MROWS - 1) / MROWS, (g.oz + MG_DEFAULT - 1) / MG_DEFAULT);
 }
 
 template <int KX, int PREC>
 hipError_t launch_kx(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
   using S = MfmaShape<KX>;
-  const size_t lds = sizeof(float) * (size_t)mfma_lds_floats(g.ky, S::STRIDE, S::HS);
+  const size_t lds = sizeof(float) * (size_t)mfma_lds_floats(g.ky, S::STRIDE, S::HS, MG_DEFAULT);
   static bool attr_set = false;  // allow the full LDS of a CU (idempotent)
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void *)conv_mfma_kernel<KX, PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float) * mfma_lds_floats(MAX_KY, S::STRIDE, S::HS)));
+                              (int)(sizeof(float) * mfma_lds_floats(MAX_KY, S::STRIDE, S::HS, MG_DEFAULT)));
     (void)hipGetLastError();
     attr_set = true;
   }

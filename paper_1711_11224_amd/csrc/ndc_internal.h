@@ -70,6 +70,28 @@ struct ConvPlan {
   int64_t nblocks;    // number of work-groups (partial-sum slots)
 };
 
+// Batched form ---------------------------------------------------------------
+// One volume of a batch (device table).  For the convolution-only batch
+// calls X is the input and R the output of the forward (the reverse for the
+// transpose); the deconvolution uses every field.
+struct BVol {
+  int m[3], p[3];
+  const float *Y, *H;
+  float *X, *Xt, *G, *R, *Rt;
+  DState *st;
+  double *stats;  // nullable, (iters+1) x 4
+  int *info;      // nullable, 2 ints
+  int64_t n, ny;  // element counts of X and Y
+  int fwd_lo, fwd_hi, adj_lo, adj_hi;  // partial-sum slot ranges of its tiles
+};
+
+// One tile of the persistent launch: volume, tile coordinates, partial slot.
+struct BTile {
+  int vol, tx, ty, tz, slot, pad0, pad1, pad2;
+};
+
+enum BatchOp { BOP_FWD = 0, BOP_ADJ = 1, BOP_INIT = 2, BOP_STEP_FWD = 3, BOP_STEP_ADJ = 4 };
+
 // Fold an n-D problem (n <= 3) into 3-D extents.
 bool fold3(int n, const int64_t *m, const int64_t *p, int64_t m3[3], int64_t p3[3]);
 Geom forward_geom(const int64_t m3[3], const int64_t p3[3]);
@@ -79,5 +101,13 @@ Geom adjoint_geom(const int64_t m3[3], const int64_t p3[3]);
 ConvPlan plan_conv(const Geom &g, int dtype, int precision);
 hipError_t launch_conv(const ConvPlan &pl, const Geom &g, int dtype, int precision, const void *in,
                        const void *H, void *out, const Epi &ep, hipStream_t s);
+
+// Batched persistent launch (conv_mfma.hip): walks tiles[0..ntiles) with a
+// grid of `grid` work-groups; mg is 2 or 4 output planes per tile.
+hipError_t launch_batch_conv(int mg, const BVol *vols, const BTile *tiles, int ntiles, int op, double *part,
+                             int grid, size_t lds_bytes, hipStream_t s);
+size_t batch_lds_bytes(int kx, int ky, int mg);
+bool batch_psf_supported(int kx, int ky);
+dim3 batch_tile_counts(int oz, int oy, int ox, int mg);
 
 }  // namespace ndc

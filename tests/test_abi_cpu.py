@@ -110,3 +110,27 @@ def test_dH_workspace_check():
     rc = lib.conv_dH_nd(3, I(m), I(p), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x10000000),
                         ctypes.c_void_p(0x20000000), F32, None, 0, None)
     assert rc == nd.NDC_EWORKSPACE
+
+
+def _plan(count, m, p, dt=F32, pr=0, tuning=None):
+    h = ctypes.c_void_p()
+    tun = None if tuning is None else (ctypes.c_int * 4)(*tuning)
+    rc = lib.ndc_batch_plan_create(count, I(m), I(p), dt, pr, tun, ctypes.byref(h))
+    return rc, h
+
+
+def test_batch_plan_argument_checks():
+    assert _plan(0, [4, 4, 4], [1, 1, 1])[0] == nd.NDC_EINVAL
+    assert _plan(1, [4, 0, 4], [1, 1, 1])[0] == nd.NDC_EINVAL
+    assert _plan(1, [4, 4, 4], [1, -1, 1])[0] == nd.NDC_EINVAL
+    assert _plan(1, [4, 4, 4], [1, 1, 1], dt=F64)[0] == nd.NDC_EUNSUPPORTED
+    assert _plan(1, [4, 4, 4], [1, 1, 1], pr=nd.NDC_PREC_BF16)[0] == nd.NDC_EUNSUPPORTED
+    assert _plan(1, [4, 4, 4], [1, 1, 17])[0] == nd.NDC_EUNSUPPORTED  # 2p_x+1 = 35 > 33
+    assert _plan(1, [4, 4, 4], [1, 1, 0])[0] == nd.NDC_EUNSUPPORTED   # 2p_x+1 = 1 < 3
+    assert _plan(2, [4, 4, 4, 5, 5, 5], [1, 1, 1, 1, 17, 1])[0] == nd.NDC_EUNSUPPORTED
+    assert _plan(1, [4, 4, 4], [1, 1, 1], tuning=[3, 2, 0, 1])[0] == nd.NDC_EINVAL
+    assert _plan(1, [4, 4, 4], [1, 1, 1], tuning=[4, 3, 0, 1])[0] == nd.NDC_EINVAL
+    assert _plan(1, [4, 4, 4], [1, 1, 1], tuning=[4, 2, 5, 1])[0] == nd.NDC_EINVAL
+    assert lib.ndc_batch_plan_create(1, I([4, 4, 4]), I([1, 1, 1]), F32, 0, None, None) == nd.NDC_EINVAL
+    assert lib.ndc_batch_workspace_bytes(None) == 0
+    lib.ndc_batch_plan_destroy(None)  # no-op

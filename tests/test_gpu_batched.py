@@ -1,0 +1,192 @@
+"""Batched form: persistent launches over many volumes with their own
+extents and PSFs, per-volume line searches, hipGraph replay, autotuner."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1711_11224_amd as m
+    import paper_1711_11224_amd.batched  # noqa: F401
+    return m
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def same(a, b):
+    """Bitwise equality that treats NaN as equal to NaN (row 0 of the stats
+    holds NaN for the undefined step size and step length)."""
+    return a.shape == b.shape and bool(torch.all((a == b) | (torch.isnan(a) & torch.isnan(b))))
+
+
+def rel_l2(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+SMALL = [((6, 20, 70), (3, 5, 9)), ((9, 17, 33), (5, 3, 3)), ((4, 40, 64), (1, 7, 31)),
+         ((12, 12, 12), (9, 9, 15)), ((3, 5, 130), (3, 3, 7)), ((7, 33, 20), (7, 33, 33))]
+
+
+def small_batch(rng):
+    xs, hs, ys = [], [], []
+    for m, k in SMALL:
+        xs.append(rng.random(m).astype(np.float32))
+        hs.append(rng.standard_normal(k).astype(np.float32))
+    return xs, hs
+
+
+@pytest.mark.parametrize("tuning", [(4, 2, 0, 1), (2, 1, 1, 1), (4, 1, 2, 0)])
+def test_batch_conv_vs_oracle(nd, tuning):
+    say("case batch conv", tuning)
+    rng = np.random.default_rng(10)
+    xs, hs = small_batch(rng)
+    plan = nd.batched.BatchPlan([m for m, _ in SMALL], [k for _, k in SMALL], tuning=tuning)
+    gx = [torch.from_numpy(x).cuda() for x in xs]
+    gh = [torch.from_numpy(h).cuda() for h in hs]
+    ys = plan.conv_full(gx, gh)
+    rs = [np.random.default_rng(i).standard_normal(tuple(y.shape)).astype(np.float32) for i, y in enumerate(ys)]
+    gs = plan.conv_adjoint([torch.from_numpy(r).cuda() for r in rs], gh)
+    for v, (x, h) in enumerate(zip(xs, hs)):
+        assert rel_l2(ys[v].cpu().numpy(), oracle.conv_full(x, h)) <= 1e-5
+        assert rel_l2(gs[v].cpu().numpy(), oracle.conv_adjoint(rs[v], h)) <= 1e-5
+    plan.close()
+
+
+def test_batch_conv_equals_single_volume_bitwise(nd):
+    """Four output planes per tile, like the single-volume kernel: same sums
+    in the same order, so every output is bitwise equal."""
+    say("case batch == single")
+    rng = np.random.default_rng(11)
+    xs, hs = small_batch(rng)
+    plan = nd.batched.BatchPlan([m for m, _ in SMALL], [k for _, k in SMALL], tuning=(4, 2, 1, 1))
+    gx = [torch.from_numpy(x).cuda() for x in xs]
+    gh = [torch.from_numpy(h).cuda() for h in hs]
+    ys = plan.conv_full(gx, gh)
+    gs = plan.conv_adjoint(ys, gh)
+    for v in range(len(SMALL)):
+        y1 = nd.conv_full_nd(gx[v], gh[v])
+        assert torch.equal(ys[v], y1)
+        assert torch.equal(gs[v], nd.conv_adjoint_nd(y1, gh[v]))
+    plan.close()
+
+
+def _deconv_inputs(rng, specs):
+    ys, hs, x0s = [], [], []
+    for m, k in specs:
+        h = synth.gaussian_psf(k, tuple(0.3 * e for e in k)).astype(np.float32)
+        xt = rng.random(m)
+        y = (oracle.conv_full(xt, h) + 0.02 * rng.standard_normal([a + b - 1 for a, b in zip(m, k)]))
+        ys.append(y.astype(np.float32))
+        hs.append(h)
+        x0s.append(np.full(m, 0.4, dtype=np.float32))
+    return ys, hs, x0s
+
+
+def test_batch_deconv_vs_oracle_and_single(nd):
+    say("case batch deconv")
+    rng = np.random.default_rng(12)
+    specs = SMALL[:4]
+    ys, hs, x0s = _deconv_inputs(rng, specs)
+    plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=(4, 2, 0, 1))
+    gy = [torch.from_numpy(a).cuda() for a in ys]
+    gh = [torch.from_numpy(a).cuda() for a in hs]
+    gx = [torch.from_numpy(a).cuda() for a in x0s]
+    xs, stats, info = plan.deconv(gy, gh, gx, 8, lam=0.1)
+    info = info.cpu().numpy()
+    for v in range(len(specs)):
+        xo, so, done, status = oracle.deconv(ys[v], hs[v], x0s[v], 8, lam=0.1)
+        assert info[v].tolist() == [done, status]
+        st = stats[v].cpu().numpy()
+        np.testing.assert_array_equal(st[1:done + 1, 2], so[1:done + 1, 2])
+        assert rel_l2(xs[v].cpu().numpy(), xo) <= 1e-5
+        assert np.all(np.abs(st[:done + 1, 0] - so[:done + 1, 0]) <= 1e-5 * np.abs(so[:done + 1, 0]))
+        # and bitwise equal to the single-volume path (same tiles, same sums)
+        x1, st1, inf1 = nd.deconv_iterate(gy[v], gh[v], torch.from_numpy(x0s[v]).cuda(), 8, lam=0.1)
+        assert torch.equal(x1, xs[v])
+        assert same(st1, stats[v])
+    plan.close()
+
+
+def test_batch_graph_replays_equal_eager(nd):
+    """The hipGraph-captured step replayed many times, with eager work and
+    synchronisations between calls, gives bitwise the same result as the
+    same kernels launched one by one."""
+    say("case batch graph vs eager")
+    rng = np.random.default_rng(13)
+    specs = SMALL[:3]
+    for trial in range(2):
+        ys, hs, x0s = _deconv_inputs(rng, specs)
+        out = {}
+        for graph in (1, 0):
+            plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=(4, 2, 0, graph))
+            gx = [torch.from_numpy(a).cuda() for a in x0s]
+            xs, stats, info = plan.deconv([torch.from_numpy(a).cuda() for a in ys],
+                                          [torch.from_numpy(a).cuda() for a in hs], gx, 6)
+            torch.cuda.synchronize()
+            _ = (torch.ones(1000, device="cuda") * 2).sum().item()  # unrelated eager work between replays
+            out[graph] = ([x.clone() for x in xs], [s.clone() for s in stats], info.clone())
+            plan.close()
+        for a, b in zip(out[1][0], out[0][0]):
+            assert torch.equal(a, b)
+        for a, b in zip(out[1][1], out[0][1]):
+            assert same(a, b)
+        assert torch.equal(out[1][2], out[0][2])
+
+
+def test_batched_workload_64_volumes(nd):
+    """The batched workload: 64 volumes of 32^3 .. 96x160x160 with their own
+    Gaussian PSFs (odd extents 9..31 per axis), 50 steps in one plan with
+    the hipGraph.  Every volume runs all steps with f strictly decreasing and
+    X >= 0; three volumes are rerun alone and must match bitwise."""
+    cfgs = synth.batched_configs(64)
+    say("case c4 batched 64")
+    ys, hs, x0s = [], [], []
+    for c in cfgs:
+        x = synth.make_objects(c)
+        fac = synth.gaussian_factors(c.psf_shape, c.sigmas)
+        h = synth.gaussian_psf(c.psf_shape, c.sigmas).astype(np.float32)
+        y = synth.add_noise(oracle.conv_full_separable(x, fac), c).astype(np.float32)
+        ys.append(torch.from_numpy(y).cuda())
+        hs.append(torch.from_numpy(h).cuda())
+        x0s.append(synth.flat_start(y, h, c.shape).astype(np.float32))
+    plan = nd.batched.BatchPlan([c.shape for c in cfgs], [c.psf_shape for c in cfgs], tuning=(4, 2, 2, 1))
+    xs = [torch.from_numpy(a).cuda() for a in x0s]
+    xs, stats, info = plan.deconv(ys, hs, xs, 50)
+    info = info.cpu().numpy()
+    assert np.all(info[:, 0] == 50) and np.all(info[:, 1] == 0)
+    for v in range(64):
+        f = stats[v].cpu().numpy()[:, 0]
+        assert np.all(np.diff(f) < 0)
+        assert float(xs[v].min()) >= 0
+    for v in (0, 17, 63):
+        x1, st1, _ = nd.deconv_iterate(ys[v], hs[v], torch.from_numpy(x0s[v]).cuda(), 50)
+        assert torch.equal(x1, xs[v])
+    plan.close()
+
+
+def test_autotuner_table(nd, tmp_path):
+    from paper_1711_11224_amd import autotune
+    say("case autotune")
+    specs = SMALL[:3]
+    shapes, psfs = [m for m, _ in specs], [k for _, k in specs]
+    table = str(tmp_path / "table.json")
+    best, times = autotune.tune(shapes, psfs, candidates=[(4, 2, 0, 1), (2, 2, 1, 1), (4, 1, 2, 1)], table=table)
+    assert best in times and times[best] == min(times.values())
+    assert autotune.best_tuning(shapes, psfs, table=table) == best
+    plan = nd.batched.plan_for(shapes, psfs, table=table)
+    assert plan.tuning == best
+    plan.close()
