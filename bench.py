@@ -97,6 +97,102 @@ def measured_traffic(kernel_key):
     return int(k["read_bytes"] + k["write_bytes"])
 
 
+def bench_differentiable(nd, torch, reps=3):
+    """Differentiable workload (X 64x256x256, PSF 41x21x21): one forward and
+    the hand-written backward (dX by the transpose, dH by the PSF-gradient
+    kernel), 3 N K multiply-adds per pass."""
+    import synth
+    from paper_1711_11224_amd.autograd import conv_full_ad
+    cfg = synth.CONFIGS["c5_diff"]
+    g = torch.Generator(device="cuda").manual_seed(4)
+    x = torch.rand(cfg.shape, device="cuda", generator=g).requires_grad_(True)
+    h = torch.tensor(synth.psf_for(cfg), dtype=torch.float32, device="cuda").requires_grad_(True)
+    gy = torch.randn([a + b - 1 for a, b in zip(cfg.shape, cfg.psf_shape)], device="cuda", generator=g)
+    N, K = int(np.prod(cfg.shape)), int(np.prod(cfg.psf_shape))
+
+    def one():
+        x.grad = None
+        h.grad = None
+        conv_full_ad(x, h).backward(gy)
+
+    one()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        one()
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # the PSF-gradient kernel alone
+    y = nd.conv_full_nd(x.detach(), h.detach())
+    e0.record(s)
+    for _ in range(reps):
+        nd.conv_dH_nd(x.detach(), gy, cfg.psf_shape)
+    e1.record(s)
+    torch.cuda.synchronize()
+    dh_ms = e0.elapsed_time(e1) / reps
+    del y
+    return {"workload": "X 64x256x256, PSF 41x21x21, FP32", "forward_backward_ms": round(ms, 3),
+            "gmacs": round(3.0 * N * K / (ms * 1e-3) / 1e9, 1), "dH_ms": round(dh_ms, 3),
+            "dH_gmacs": round(N * K / (dh_ms * 1e-3) / 1e9, 1)}
+
+
+def bench_batched(nd, torch, steps=5, table=None):
+    """Batched workload: 64 volumes of 32^3 .. 96x160x160, each with its own
+    Gaussian PSF of odd extents 9..31, FP32, one hipGraph-captured step per
+    iteration, tuning from the autotuner's table."""
+    import synth
+    from paper_1711_11224_amd.batched import plan_for
+    cfgs = synth.batched_configs(64)
+    shapes, psfs = [c.shape for c in cfgs], [c.psf_shape for c in cfgs]
+    t = time.time()
+    plan = plan_for(shapes, psfs, tuning="auto", table=table)
+    tune_s = time.time() - t
+    ys, hs, xs = [], [], []
+    for c in cfgs:
+        xt = torch.tensor(synth.make_objects(c), dtype=torch.float32, device="cuda")
+        h = torch.tensor(synth.psf_for(c), dtype=torch.float32, device="cuda")
+        y = synth.add_noise(nd.conv_full_nd(xt, h).cpu().numpy(), c).astype(np.float32)
+        ys.append(torch.from_numpy(y).cuda())
+        hs.append(h)
+        xs.append(torch.from_numpy(synth.flat_start(y, synth.psf_for(c), c.shape).astype(np.float32)).cuda())
+    macs = 2.0 * sum(int(np.prod(c.shape)) * int(np.prod(c.psf_shape)) for c in cfgs)
+    plan.deconv(ys, hs, xs, 1)  # warm-up (captures the graph)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    _, stats, info = plan.deconv(ys, hs, xs, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    done = int(info[:, 0].min())
+    pair_ms = time_plan_pair(plan, torch, xs, hs)
+    plan.close()
+    return {"workload": "64 volumes 32^3..96x160x160, PSFs 9..31 per axis, FP32", "tuning": list(plan.tuning),
+            "tune_or_lookup_s": round(tune_s, 2), "steps": steps, "steps_accepted_min": done,
+            "ms_per_step": round(ms / steps, 3), "iters_per_s": round(steps / (ms * 1e-3), 2),
+            "gmacs": round(macs * done / (ms * 1e-3) / 1e9, 1),
+            "conv_pair_ms": round(pair_ms, 3), "conv_pair_gmacs": round(macs / (pair_ms * 1e-3) / 1e9, 1)}
+
+
+def time_plan_pair(plan, torch, xs, hs, reps=3):
+    ys = plan.conv_full(xs, hs)
+    gs = plan.conv_adjoint(ys, hs)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        plan.conv_full(xs, hs, ys=ys)
+        plan.conv_adjoint(ys, hs, xs=gs)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def cpu_baseline(cfg, target_s=15.0):
     """The FP64 oracle, as it stands, on a bounded random sample of forward
     and transpose outputs of the same workload (each output is a full
@@ -139,6 +235,8 @@ def main():
     ap.add_argument("--pair-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precisions", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the differentiable and batched workloads")
+    ap.add_argument("--tuning-table", default=None, help="autotuner table (default: the package's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (scales HBM counters)")
     args = ap.parse_args()
@@ -228,6 +326,11 @@ def main():
         "roofline": roofline,
         "precisions": precisions,
     }
+    if not args.no_extra:
+        out["differentiable"] = bench_differentiable(nd, torch)
+        log("differentiable:", out["differentiable"])
+        out["batched"] = bench_batched(nd, torch, table=args.tuning_table)
+        log("batched:", out["batched"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
