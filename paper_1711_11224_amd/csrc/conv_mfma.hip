@@ -5,7 +5,7 @@ namespace ndc {
 namespace {
 using namespace mfma;
 
-template <int KX, int PREC>
+template <int KX, int PREC, int XB>
 __global__ __launch_bounds__(MT, 2) void conv_mfma_kernel(const float *__restrict__ in, const float *__restrict__ H,
                                                           float *__restrict__ out, Geom g, Epi ep, int nbx, int nby,
                                                           int nbz) {
@@ -17,29 +17,46 @@ __global__ __launch_bounds__(MT, 2) void conv_mfma_kernel(const float *__restric
   // on expensive mid-volume tiles; measured 5% slower for the forward.)
   const int id = blockIdx.x;
   (void)nbz;
-  mfma_tile<KX, PREC, MG_DEFAULT>(in, H, out, g, ep, id % nbx, (id / nbx) % nby, id / (nbx * nby), id, lds, red);
+  mfma_tile<KX, PREC, MG_DEFAULT, XB>(in, H, out, g, ep, id % nbx, (id / nbx) % nby, id / (nbx * nby), id, lds,
+                                     red);
 }
 
-dim3 tile_counts(const Geom &g) {
-  return dim3((g.ox + MCOLS - 1) / MCOLS, (g.oy + MROWS - 1) / MROWS, (g.oz + MG_DEFAULT - 1) / MG_DEFAULT);
+// x-blocks per instruction for a launch (see TileDims): 32-column tiles when
+// they pad the output's x extent less than 64-column ones, and for the bf16
+// forms (measured faster at every workload size); otherwise 64 columns.
+int choose_xb(const Geom &g, int precision) {
+  const int w16 = (g.ox + 63) / 64 * 64 - g.ox, w8 = (g.ox + 31) / 32 * 32 - g.ox;
+  return (w8 < w16 || precision != NDC_PREC_NATIVE) ? 8 : 16;
+}
+
+dim3 tile_counts(const Geom &g, int xb) {
+  const int cols = 4 * xb, rows = 256 / xb;
+  return dim3((g.ox + cols - 1) / cols, (g.oy + rows - 1) / rows, (g.oz + MG_DEFAULT - 1) / MG_DEFAULT);
+}
+
+template <int KX, int PREC, int XB>
+hipError_t launch_kx_xb(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
+  using S = MfmaShape<KX, XB>;
+  const size_t lds = sizeof(float) * (size_t)S::lds_floats(g.ky, MG_DEFAULT, PREC);
+  static bool attr_set = false;  // allow the full LDS of a CU (idempotent)
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void *)conv_mfma_kernel<KX, PREC, XB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(float) * S::lds_floats(MAX_KY, MG_DEFAULT, PREC)));
+    (void)hipGetLastError();
+    attr_set = true;
+  }
+  const dim3 t = tile_counts(g, XB);
+  const unsigned total = t.x * t.y * t.z;
+  hipLaunchKernelGGL((conv_mfma_kernel<KX, PREC, XB>), dim3(total), dim3(MT), lds, s, (const float *)in,
+                     (const float *)H, (float *)out, g, ep, (int)t.x, (int)t.y, (int)t.z);
+  return hipGetLastError();
 }
 
 template <int KX, int PREC>
 hipError_t launch_kx(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
-  using S = MfmaShape<KX>;
-  const size_t lds = sizeof(float) * (size_t)mfma_lds_floats(g.ky, S::STRIDE, S::HS, MG_DEFAULT);
-  static bool attr_set = false;  // allow the full LDS of a CU (idempotent)
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void *)conv_mfma_kernel<KX, PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(float) * mfma_lds_floats(MAX_KY, S::STRIDE, S::HS, MG_DEFAULT)));
-    (void)hipGetLastError();
-    attr_set = true;
-  }
-  const dim3 t = tile_counts(g);
-  const unsigned total = t.x * t.y * t.z;
-  hipLaunchKernelGGL((conv_mfma_kernel<KX, PREC>), dim3(total), dim3(MT), lds, s, (const float *)in,
-                     (const float *)H, (float *)out, g, ep, (int)t.x, (int)t.y, (int)t.z);
-  return hipGetLastError();
+  if (choose_xb(g, PREC) == 8) return launch_kx_xb<KX, PREC, 8>(g, in, H, out, ep, s);
+  return launch_kx_xb<KX, PREC, 16>(g, in, H, out, ep, s);
 }
 
 template <int PREC>
@@ -63,10 +80,10 @@ bool mfma_supported(const Geom &g, int dtype, int) {
   return true;
 }
 
-ConvPlan plan_conv_mfma(const Geom &g, int, int) {
+ConvPlan plan_conv_mfma(const Geom &g, int, int precision) {
   ConvPlan pl;
   pl.variant = 1;
-  const dim3 t = tile_counts(g);
+  const dim3 t = tile_counts(g, choose_xb(g, precision));
   pl.grid = dim3(t.x * t.y * t.z);
   pl.block = dim3(MT);
   pl.lds_bytes = 0;

@@ -53,21 +53,42 @@ constexpr int MROWS = 16;     // output rows per work-group
 constexpr int MCOLS = 64;     // output columns per work-group
 constexpr int MAX_KY = 33;
 
-template <int KX>
+// Tile shape: XB of the 16 instruction blocks lie along x (4 columns each),
+// the other 16/XB stack along y, so a wave covers 4*16/XB rows x 4*XB columns
+// and a work-group (4 waves) 16*16/XB rows x 4*XB columns.
+template <int XB>
+struct TileDims {
+  static constexpr int RG = 16 / XB;      // row groups per instruction
+  static constexpr int WR = 4 * RG;       // rows per wave
+  static constexpr int ROWS = 4 * WR;     // rows per work-group
+  static constexpr int COLS = 4 * XB;     // columns per work-group
+};
+
+template <int KX, int XB = 16>
 struct MfmaShape {
   static constexpr int KS = KX + 3;               // unit steps per PSF row
   static constexpr int NC = (KS + 15) / 16;       // FP32: broadcast A registers per row
   static constexpr int NW = (KS + 3) / 4;         // float4 input windows per lane (= bf16 chunks)
   static constexpr int NCB = (NW + 15) / 16;      // bf16: broadcast A registers per row
-  static constexpr int TCOLS = 60 + 4 * NW;       // staged input columns
-  static constexpr int STRIDE = ((TCOLS + 23) / 32) * 32 + 8;  // = 8 mod 32 floats
+  static constexpr int TCOLS = 4 * XB - 4 + 4 * NW;               // staged input columns
+  static constexpr int STRIDE = ((TCOLS + 23) / 32) * 32 + 8;     // = 8 mod 32 floats
   static constexpr int HS = 16 * NC + 4;          // LDS PSF row stride (>= 4*NW + 3)
-  static constexpr int NIN = ((MROWS + MAX_KY - 1) * TCOLS + MT - 1) / MT;
+  // bf16 input tiles: row stride in bf16 elements, = 16 mod 64 so the 8-byte
+  // window reads of 16 lanes (4 rows x 4 x-blocks) hit distinct bank pairs
+  static constexpr int STRIDE_B = ((TCOLS + 47) / 64) * 64 + 16;
+  static constexpr int NIN = ((TileDims<XB>::ROWS + MAX_KY - 1) * TCOLS + MT - 1) / MT;
+  // floats of LDS one staged input plane takes (planes: 1 FP32, 1 bf16, 2 bf16 hi/lo)
+  __host__ __device__ static constexpr int tile_floats(int rows, int prec) {
+    return prec == 0 ? rows * STRIDE : ((prec == 2 ? 2 : 1) * rows * STRIDE_B / 2 + 3) / 4 * 4;
+  }
+  __host__ __device__ static constexpr int lds_floats(int ky, int mg, int prec) {
+    return 2 * tile_floats(TileDims<XB>::ROWS + ky - 1, prec) + (mg + 1) * ky * HS;
+  }
   static constexpr int NH = (MAX_KY * HS + MT - 1) / MT;
 };
 
-__host__ __device__ constexpr int mfma_lds_floats(int ky, int stride, int hs, int mg) {
-  return 2 * (MROWS + ky - 1) * stride + (mg + 1) * ky * hs;
+__host__ __device__ constexpr int mfma_lds_floats(int ky, int stride, int hs, int mg, int rows = MROWS) {
+  return 2 * (rows + ky - 1) * stride + (mg + 1) * ky * hs;
 }
 
 __device__ __forceinline__ v4s to_bf16(v4f v) { return __builtin_bit_cast(v4s, __builtin_convertvector(v, v4bf)); }
@@ -80,21 +101,26 @@ __device__ __forceinline__ void split_bf16(v4f v, v4s &hi, v4s &lo) {
 // One output tile (G z-planes x 16 rows x 64 columns at tile coordinates
 // tx, ty, tz) of the correlation; `slot` is the tile's partial-sum slot.
 // All threads of the work-group call it; it leaves LDS free on return.
-template <int KX, int PREC, int MG>
+template <int KX, int PREC, int MG, int XB = 16>
 __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const float *__restrict__ H,
                                           float *__restrict__ out, const Geom &g, const Epi &ep, int tx, int ty,
                                           int tz, int64_t slot, float *lds, double (*red)[2]) {
-  using S = MfmaShape<KX>;
-  const int rows = MROWS + g.ky - 1;
+  using S = MfmaShape<KX, XB>;
+  using T = TileDims<XB>;
+  const int rows = T::ROWS + g.ky - 1;
+  const int tfl = S::tile_floats(rows, PREC);
   float *tile0 = lds;
-  float *tile1 = lds + rows * S::STRIDE;
-  float *ring = lds + 2 * rows * S::STRIDE;
+  float *tile1 = lds + tfl;
+  float *ring = lds + 2 * tfl;
   const int hplane = g.ky * S::HS;
+  const int lo_off = rows * S::STRIDE_B;  // bf16 elements from hi plane to lo plane (split)
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
-  const int bb = lane >> 2, jj = lane & 3;                  // block, row within block (B and D)
-  const int x0 = tx * MCOLS, y0 = ty * MROWS, z0 = tz * MG;
+  const int bb = lane >> 2, jj = lane & 3;  // instruction block, row (B, D) or step offset (A)
+  const int xb = bb % XB, rg = bb / XB;       // x-block and row group of this lane's outputs
+  const int wrow = w * T::WR + rg * 4 + jj;   // output row within the tile
+  const int x0 = tx * T::COLS, y0 = ty * T::ROWS, z0 = tz * MG;
 
   // input planes that reach this tile, clipped to the input
   const int r_lo = max(0, z0 - g.offz);
@@ -120,7 +146,16 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
     for (int u = 0; u < S::NIN; ++u) {
       const int e = tid + u * MT;
       const int r = e / S::TCOLS, q = e - r * S::TCOLS;
-      if (r < rows) t[r * S::STRIDE + q] = inreg[u];
+      if (r < rows) {
+        if constexpr (PREC == PREC_NATIVE_) {
+          t[r * S::STRIDE + q] = inreg[u];
+        } else {  // rounded once here instead of once per PSF row
+          __bf16 *tb = (__bf16 *)t;
+          const __bf16 hi = (__bf16)inreg[u];
+          tb[r * S::STRIDE_B + q] = hi;
+          if constexpr (PREC == PREC_SPLIT_) tb[lo_off + r * S::STRIDE_B + q] = (__bf16)(inreg[u] - (float)hi);
+        }
+      }
     }
   };
   auto load_h = [&](int a) {  // PSF plane a of Hc, rows padded with 3 leading zeros
@@ -162,9 +197,9 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
     __syncthreads();
 
     // rows of this wave's outputs that reach the input, as a tap range
-    const int b_lo = max(0, g.offy - y0 - 4 * w - 3);
-    const int b_hi = min(g.ky - 1, g.iy - 1 + g.offy - y0 - 4 * w);
-    const bool wave_live = (y0 + 4 * w < g.oy);
+    const int b_lo = max(0, g.offy - y0 - w * T::WR - (T::WR - 1));
+    const int b_hi = min(g.ky - 1, g.iy - 1 + g.offy - y0 - w * T::WR);
+    const bool wave_live = (y0 + w * T::WR < g.oy);
 
     for (int zin = r_lo; zin <= r_hi; ++zin) {
       const float *tile = ((zin - r_lo) & 1) ? tile1 : tile0;
@@ -183,13 +218,13 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
           live[q] = aq[q] >= 0 && aq[q] < g.kz && z0 + q < g.oz;
         }
         for (int b = b_lo; b <= b_hi; ++b) {
-          // B operand: consecutive inputs of row (4w + jj + b), column 4*bb + k
-          const float *src = tile + (4 * w + jj + b) * S::STRIDE + 4 * bb;
-          v4f win[S::NW];
-#pragma unroll
-          for (int u = 0; u < S::NW; ++u) win[u] = *(const v4f *)(src + 4 * u);
           v4f d[MG];
           if constexpr (PREC == PREC_NATIVE_) {
+            // B operand: consecutive inputs of row (wrow + b), column 4*xb + k
+            const float *src = tile + (wrow + b) * S::STRIDE + 4 * xb;
+            v4f win[S::NW];
+#pragma unroll
+            for (int u = 0; u < S::NW; ++u) win[u] = *(const v4f *)(src + 4 * u);
             // A operand: lane 4s+i holds Hc_row[16c + s - i]
             float hv[MG][S::NC];
 #pragma unroll
@@ -227,13 +262,12 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
                   ahi[q][r] = to_bf16(hv4);
               }
             }
+            const short *srcb = (const short *)tile + (wrow + b) * S::STRIDE_B + 4 * xb;
             static_for<0, S::NW>([&](auto cc) {
               constexpr int c = decltype(cc)::value;
-              v4s bhi, blo;
-              if constexpr (PREC == PREC_SPLIT_)
-                split_bf16(win[c], bhi, blo);
-              else
-                bhi = to_bf16(win[c]);
+              const v4s bhi = *(const v4s *)(srcb + 4 * c);
+              v4s blo;
+              if constexpr (PREC == PREC_SPLIT_) blo = *(const v4s *)(srcb + lo_off + 4 * c);
               static_for<0, MG>([&](auto qc) {
                 constexpr int q = decltype(qc)::value;
                 const v4f c0 = c == 0 ? (v4f){0.f, 0.f, 0.f, 0.f} : d[q];
@@ -258,9 +292,9 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
     }
   }
 
-  // Epilogue: lane (bb, jj) holds x = x0 + 4bb + i, row y0 + 4w + jj -----------
+  // Epilogue: lane (bb, jj) holds x = x0 + 4xb + i, row y0 + wrow -------------
   double s0 = 0.0, s1 = 0.0;
-  const int y = y0 + 4 * w + jj;
+  const int y = y0 + wrow;
   if (y < g.oy) {
 #pragma unroll
     for (int q = 0; q < MG; ++q) {
@@ -269,7 +303,7 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
         const int64_t rowbase = ((int64_t)z * g.oy + y) * g.ox;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int x = x0 + 4 * bb + i;
+          const int x = x0 + 4 * xb + i;
           if (x < g.ox) apply_epilogue<float>(out, rowbase + x, acc[q][i], ep, s0, s1);
         }
       }
