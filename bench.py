@@ -193,6 +193,29 @@ def time_plan_pair(plan, torch, xs, hs, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
+def bench_small_psf(nd, torch, reps=5):
+    """Small-PSF sweep on the metric volume (128x512x512), Gaussian PSFs 3^3,
+    5^3, 7^3: HBM-bound operators, reported as algorithmic GB/s (4 (N + N_Y)
+    bytes per operator: read one side, write the other) against 8 TB/s."""
+    import synth
+    m = synth.CONFIGS["c3_metric"].shape
+    g = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.rand(m, device="cuda", generator=g)
+    out = {}
+    for k, sig in synth.SWEEP_PSFS.items():
+        h = torch.tensor(synth.gaussian_psf((k, k, k), sig), dtype=torch.float32, device="cuda")
+        fwd, adj = time_pairs(nd, torch, x, h, "fp32", reps)
+        N = int(np.prod(m))
+        NY = int(np.prod([a + k - 1 for a in m]))
+        by = 4.0 * (N + NY)
+        out["%d^3" % k] = {"forward_ms": round(fwd, 4), "transpose_ms": round(adj, 4),
+                           "forward_GBps": round(by / (fwd * 1e-3) / 1e9, 1),
+                           "transpose_GBps": round(by / (adj * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(by / (min(fwd, adj) * 1e-3) / 8e12, 3),
+                           "gmacs": round(2.0 * N * k ** 3 / ((fwd + adj) * 1e-3) / 1e9, 1)}
+    return out
+
+
 def cpu_baseline(cfg, target_s=15.0):
     """The FP64 oracle, as it stands, on a bounded random sample of forward
     and transpose outputs of the same workload (each output is a full
@@ -327,6 +350,8 @@ def main():
         "precisions": precisions,
     }
     if not args.no_extra:
+        out["small_psf"] = bench_small_psf(nd, torch)
+        log("small psf:", out["small_psf"])
         out["differentiable"] = bench_differentiable(nd, torch)
         log("differentiable:", out["differentiable"])
         out["batched"] = bench_batched(nd, torch, table=args.tuning_table)

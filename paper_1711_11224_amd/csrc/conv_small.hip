@@ -1,0 +1,212 @@
+// Streaming correlation kernel for small PSFs (every axis <= 7 taps), where
+// the operators are bound by HBM rather than by arithmetic.
+//
+// out[s] = sum_t Hc[t] in[s + t - off]  (see Geom), FP32 or FP64.
+//
+// A work-group owns an 8-row x 128-column column of the output and walks it
+// along z, reading every input plane of its column from HBM once:
+//   * the next input plane is prefetched into registers while the current
+//     one (double-buffered in LDS) is consumed;
+//   * each thread keeps 4 consecutive x outputs; for every tap row b it loads
+//     a (4 + kx - 1)-wide window once and applies it to all kz output planes
+//     the input plane reaches (kz x kx x 4 FMAs per window);
+//   * per-output partial sums of each input plane are added to a ring of kz
+//     accumulator planes in LDS that only the owning thread touches, and an
+//     output plane is finished (fused epilogue) when its last input plane has
+//     been added.
+// Taps live in LDS (rows padded to 8) and are read as uniform float4.
+#include "ndc_device.h"
+#include "ndc_internal.h"
+
+namespace ndc {
+namespace {
+
+constexpr int ST = 256;          // threads
+constexpr int SRX = 4;           // x outputs per thread
+constexpr int STX = 32 * SRX;    // 128 output columns
+constexpr int STY = ST / 32;     // 8 output rows
+constexpr int SMAXK = 7;         // max taps per axis
+constexpr int SZC = 32;          // output planes per work-group
+constexpr int SCOLS = STX + SMAXK - 1;              // staged columns (134)
+constexpr int SSTRIDE = (SCOLS + 3) / 4 * 4 + 4;    // 140
+constexpr int SROWS = STY + SMAXK - 1;              // 14
+constexpr int SPLANE = SROWS * SSTRIDE;
+constexpr int SNIN = (SROWS * SCOLS + ST - 1) / ST; // staging registers per thread
+
+template <typename T>
+__host__ __device__ constexpr size_t small_lds_bytes(int kz) {
+  // two input planes, kz accumulator planes (4 x 256 values), taps (kz*7 rows of 8)
+  return sizeof(T) * ((size_t)2 * SPLANE + (size_t)kz * SRX * ST + (size_t)SMAXK * SMAXK * 8);
+}
+
+template <typename T, int KX>
+__global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in, const T *__restrict__ H,
+                                                        T *__restrict__ out, Geom g, Epi ep, int nbx, int nby) {
+  if (ep.phase && !((1 << *ep.phase) & ep.phase_mask)) return;
+  extern __shared__ __align__(16) unsigned char small_lds[];
+  T *planes = (T *)small_lds;                  // 2 x SPLANE
+  T *accs = planes + 2 * SPLANE;               // kz x SRX x ST (thread-private slots)
+  T *taps = accs + (size_t)g.kz * SRX * ST;    // [a][b][8]
+  __shared__ double red[ST / 64][2];
+
+  const int id = blockIdx.x;
+  const int tx = id % nbx, ty = (id / nbx) % nby, tz = id / (nbx * nby);
+  const int x0 = tx * STX, y0 = ty * STY, zlo = tz * SZC, zhi = min(g.oz, zlo + SZC);
+  const int tid = threadIdx.x, lx = tid % 32, ly = tid / 32;
+  const int rows = STY + g.ky - 1, cols = STX + KX - 1;
+  double s0 = 0.0, s1 = 0.0;
+
+  // taps, flipped for the forward operator, rows padded with zeros to 8
+  for (int e = tid; e < g.kz * g.ky * 8; e += ST) {
+    const int c = e % 8, ab = e / 8, b = ab % g.ky, a = ab / g.ky;
+    T v = (T)0;
+    if (c < KX) {
+      const int ha = g.flip ? g.kz - 1 - a : a, hb = g.flip ? g.ky - 1 - b : b, hc = g.flip ? KX - 1 - c : c;
+      v = H[((int64_t)ha * g.ky + hb) * KX + hc];
+    }
+    taps[e] = v;
+  }
+
+  auto emit = [&](int z, const T *acc) {  // finished output plane z
+    const int y = y0 + ly;
+    if (y < g.oy) {
+      const int64_t rowbase = ((int64_t)z * g.oy + y) * g.ox;
+#pragma unroll
+      for (int r = 0; r < SRX; ++r) {
+        const int x = x0 + lx * SRX + r;
+        if (x < g.ox) apply_epilogue<T>(out, rowbase + x, acc[r], ep, s0, s1);
+      }
+    }
+  };
+  // input planes of output plane z: [max(0, z-offz), min(iz-1, z-offz+kz-1)]
+  auto first_in = [&](int z) { return max(0, z - g.offz); };
+  auto last_in = [&](int z) { return min(g.iz - 1, z - g.offz + g.kz - 1); };
+
+  // output planes that no input plane reaches are zero
+  for (int z = zlo; z < zhi; ++z)
+    if (first_in(z) > last_in(z)) {
+      const T zero[SRX] = {};
+      emit(z, zero);
+    }
+
+  const int r_lo = max(0, zlo - g.offz), r_hi = min(g.iz - 1, zhi - 1 + g.kz - 1 - g.offz);
+  T inreg[SNIN];
+  auto load_plane = [&](int zin) {
+#pragma unroll
+    for (int u = 0; u < SNIN; ++u) {
+      const int e = tid + u * ST;
+      const int r = e / SCOLS, q = e - r * SCOLS;
+      const int yin = y0 + r - g.offy, xin = x0 + q - g.offx;
+      T v = (T)0;
+      if (r < rows && q < cols && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix)
+        v = in[((int64_t)zin * g.iy + yin) * g.ix + xin];
+      inreg[u] = v;
+    }
+  };
+  if (r_lo <= r_hi) load_plane(r_lo);
+  for (int zin = r_lo; zin <= r_hi; ++zin) {
+    T *pl = planes + (zin & 1) * SPLANE;
+    __syncthreads();  // the buffer being filled is no longer read; taps are visible
+#pragma unroll
+    for (int u = 0; u < SNIN; ++u) {
+      const int e = tid + u * ST;
+      const int r = e / SCOLS, q = e - r * SCOLS;
+      if (r < SROWS) pl[r * SSTRIDE + q] = inreg[u];
+    }
+    __syncthreads();
+    if (zin < r_hi) load_plane(zin + 1);
+
+    // output plane z_a = zin + offz - a receives tap plane a of this input plane
+    T part[SMAXK][SRX];
+    bool live[SMAXK];
+#pragma unroll
+    for (int a = 0; a < SMAXK; ++a) {
+      const int z = zin + g.offz - a;
+      live[a] = a < g.kz && z >= zlo && z < zhi;
+#pragma unroll
+      for (int r = 0; r < SRX; ++r) part[a][r] = (T)0;
+    }
+    for (int b = 0; b < g.ky; ++b) {
+      const T *src = pl + (ly + b) * SSTRIDE + lx * SRX;
+      T w[SRX + KX - 1];
+#pragma unroll
+      for (int u = 0; u < SRX + KX - 1; ++u) w[u] = src[u];
+#pragma unroll
+      for (int a = 0; a < SMAXK; ++a) {
+        if (live[a]) {
+          const T *hrow = taps + (a * g.ky + b) * 8;
+#pragma unroll
+          for (int c = 0; c < KX; ++c) {
+            const T hv = hrow[c];
+#pragma unroll
+            for (int r = 0; r < SRX; ++r) part[a][r] += hv * w[r + c];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < SMAXK; ++a) {
+      if (live[a]) {
+        const int z = zin + g.offz - a;
+        T *slot = accs + (size_t)(z % g.kz) * SRX * ST + tid;
+        T acc[SRX];
+#pragma unroll
+        for (int r = 0; r < SRX; ++r) acc[r] = (zin == first_in(z) ? (T)0 : slot[r * ST]) + part[a][r];
+        if (zin == last_in(z)) {
+          emit(z, acc);
+        } else {
+#pragma unroll
+          for (int r = 0; r < SRX; ++r) slot[r * ST] = acc[r];
+        }
+      }
+    }
+  }
+
+  if (ep.mode != EPI_STORE) {
+    block_sum2(s0, s1, red);
+    if (tid == 0) {
+      ep.part[2 * (int64_t)id] = s0;
+      ep.part[2 * (int64_t)id + 1] = s1;
+    }
+  }
+}
+
+template <typename T, int KX>
+hipError_t launch_small_t(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
+  const int nbx = (g.ox + STX - 1) / STX, nby = (g.oy + STY - 1) / STY, nbz = (g.oz + SZC - 1) / SZC;
+  hipLaunchKernelGGL((conv_small_kernel<T, KX>), dim3(nbx * nby * nbz), dim3(ST), small_lds_bytes<T>(g.kz), s,
+                     (const T *)in, (const T *)H, (T *)out, g, ep, nbx, nby);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_small_dt(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
+  switch (g.kx) {
+    case 1: return launch_small_t<T, 1>(g, in, H, out, ep, s);
+    case 3: return launch_small_t<T, 3>(g, in, H, out, ep, s);
+    case 5: return launch_small_t<T, 5>(g, in, H, out, ep, s);
+    case 7: return launch_small_t<T, 7>(g, in, H, out, ep, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool small_supported(const Geom &g, int dtype, int precision) {
+  if (precision != NDC_PREC_NATIVE) return false;
+  if (g.kx > SMAXK || g.ky > SMAXK || g.kz > SMAXK || !(g.kx & 1)) return false;
+  const size_t bytes = dtype == NDC_F64 ? small_lds_bytes<double>(g.kz) : small_lds_bytes<float>(g.kz);
+  return bytes <= 64 * 1024;
+}
+
+int64_t small_blocks(const Geom &g) {
+  return (int64_t)((g.ox + STX - 1) / STX) * ((g.oy + STY - 1) / STY) * ((g.oz + SZC - 1) / SZC);
+}
+
+hipError_t launch_conv_small(const Geom &g, int dtype, const void *in, const void *H, void *out, const Epi &ep,
+                             hipStream_t s) {
+  if (dtype == NDC_F64) return launch_small_dt<double>(g, in, H, out, ep, s);
+  return launch_small_dt<float>(g, in, H, out, ep, s);
+}
+
+}  // namespace ndc
