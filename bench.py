@@ -91,9 +91,10 @@ def measured_traffic(kernel_key):
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_1711_11224_amd", "csrc", "*"))):
         h.update(open(p, "rb").read())
-    k = rec.get("kernels", {}).get(kernel_key)
-    if rec.get("csrc_sha256") != h.hexdigest() or not k:
+    k = [v for key, v in rec.get("kernels", {}).items() if key.split("/")[0] == kernel_key]
+    if rec.get("csrc_sha256") != h.hexdigest() or len(k) != 1:
         return None
+    k = k[0]
     return int(k["read_bytes"] + k["write_bytes"])
 
 
@@ -326,8 +327,9 @@ def main():
                 "kernel_ms": round(dom_ms, 3)}
 
     if prec == "fp32":
-        key = "void ndc::conv_mfma_f32_kernel<31>/%d" % (3760128 if fwd_ms >= adj_ms else 2097152)
-        roofline["traffic"] = measured_traffic(key)
+        # forward: 32-column tiles (its x extent 542 pads less); transpose: 64-column tiles
+        name = "void ndc::conv_mfma_kernel<31, 0, %d>" % (8 if fwd_ms >= adj_ms else 16)
+        roofline["traffic"] = measured_traffic(name)
 
     precisions = {}
     if not args.no_precisions:
