@@ -5,10 +5,10 @@
 // kernel splits the contraction (split-K over X's z-planes) and parallelises
 // over PSF planes a:
 //   work-group (a, split s): one PSF plane, X planes [s*zc, (s+1)*zc);
-//   thread (b, cg): PSF row b, taps c = 8cg .. 8cg+7 of that row.
+//   thread b + ky*cg: PSF row b, taps c = 8cg .. 8cg+7 of that row.
 // X and G tiles of 8 rows x 128 columns are staged in LDS; every thread
 // reads the same X values (LDS broadcast) and a sliding 12-wide window of its
-// G row, 32 FMAs per 4 LDS reads.  Sums are blocked per staged tile, and the
+// G row, 32 FMAs per 4 LDS reads.  Threads are numbered along b first.  Sums are blocked per staged tile, and the
 // per-split planes are added in fixed order in double precision afterwards.
 #include "ndc_device.h"
 #include "ndc_internal.h"
@@ -35,8 +35,10 @@ __global__ void dh_kernel(const T *__restrict__ X, const T *__restrict__ G, T *_
   T *xs = (T *)dh_lds;             // DYC x DXC
   T *gs = xs + DYC * DXC;          // (DYC + ky - 1) x gstride
   const int a = blockIdx.x % d.kz, s = blockIdx.x / d.kz;
-  const int tid = threadIdx.x, b = tid / d.ncg, cg = tid - b * d.ncg;
-  const bool active = b < d.ky;
+  // lanes run along b first: with the G row stride = 4 mod 32 floats, eight
+  // consecutive lanes' 16-byte window reads land on distinct bank groups
+  const int tid = threadIdx.x, cg = tid / d.ky, b = tid - cg * d.ky;
+  const bool active = cg < d.ncg;
   const int c0 = DCT * cg;
   const int grow = DYC + d.ky - 1;
 
@@ -110,7 +112,7 @@ DhGeom dh_geom(const int64_t m3[3], const int64_t p3[3]) {
   if (want < 1) want = 1;
   d.zc = (d.mz + want - 1) / want;
   d.nsplit = (d.mz + d.zc - 1) / d.zc;
-  d.gstride = ((DXC + DCT * d.ncg + 4 + 3) / 4) * 4;
+  d.gstride = ((DXC + DCT * d.ncg + 4 + 27) / 32) * 32 + 4;  // >= needed columns, = 4 mod 32
   return d;
 }
 

@@ -82,13 +82,13 @@ struct MfmaShape {
     return prec == 0 ? rows * STRIDE : ((prec == 2 ? 2 : 1) * rows * STRIDE_B / 2 + 3) / 4 * 4;
   }
   __host__ __device__ static constexpr int lds_floats(int ky, int mg, int prec) {
-    return 2 * tile_floats(TileDims<XB>::ROWS + ky - 1, prec) + (mg + 1) * ky * HS;
+    return 2 * tile_floats(TileDims<XB>::ROWS + ky - 1, prec) + (mg + 1) * ky * HS + HS;  // + zero row
   }
   static constexpr int NH = (MAX_KY * HS + MT - 1) / MT;
 };
 
 __host__ __device__ constexpr int mfma_lds_floats(int ky, int stride, int hs, int mg, int rows = MROWS) {
-  return 2 * (rows + ky - 1) * stride + (mg + 1) * ky * hs;
+  return 2 * (rows + ky - 1) * stride + (mg + 1) * ky * hs + hs;  // + zero row
 }
 
 __device__ __forceinline__ v4s to_bf16(v4f v) { return __builtin_bit_cast(v4s, __builtin_convertvector(v, v4bf)); }
@@ -112,6 +112,7 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
   float *tile0 = lds;
   float *tile1 = lds + tfl;
   float *ring = lds + 2 * tfl;
+  float *zrow = ring + (MG + 1) * g.ky * S::HS;  // HS zeros: A operand of planes out of reach
   const int hplane = g.ky * S::HS;
   const int lo_off = rows * S::STRIDE_B;  // bf16 elements from hi plane to lo plane (split)
 
@@ -194,6 +195,7 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
       load_h(a);
       store_h(a);
     }
+    for (int e = tid; e < S::HS; e += MT) zrow[e] = 0.f;
     __syncthreads();
 
     // rows of this wave's outputs that reach the input, as a tap range
@@ -217,45 +219,61 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
           aq[q] = zin - z0 - q + g.offz;
           live[q] = aq[q] >= 0 && aq[q] < g.kz && z0 + q < g.oz;
         }
-        for (int b = b_lo; b <= b_hi; ++b) {
-          v4f d[MG];
+        {
           if constexpr (PREC == PREC_NATIVE_) {
-            // B operand: consecutive inputs of row (wrow + b), column 4*xb + k
-            const float *src = tile + (wrow + b) * S::STRIDE + 4 * xb;
-            v4f win[S::NW];
-#pragma unroll
-            for (int u = 0; u < S::NW; ++u) win[u] = *(const v4f *)(src + 4 * u);
-            // A operand: lane 4s+i holds Hc_row[16c + s - i]
-            float hv[MG][S::NC];
+            // B operand: consecutive inputs of row (wrow + b), column 4*xb + k;
+            // A operand: lane 4s+i holds Hc_row[16c + s - i], or 0 from the
+            // zero row when output plane q is not reached (no branch).
+            const float *hbase[MG];
+            int hstep[MG];
 #pragma unroll
             for (int q = 0; q < MG; ++q) {
-              const float *hrow = ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane + b * S::HS + 3 + bb - jj;
-#pragma unroll
-              for (int c = 0; c < S::NC; ++c) hv[q][c] = live[q] ? hrow[16 * c] : 0.f;
+              hbase[q] = (live[q] ? ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane : zrow) + 3 + bb - jj;
+              hstep[q] = live[q] ? S::HS : 0;
             }
-            static_for<0, S::KS>([&](auto kc) {
-              constexpr int k = decltype(kc)::value;
-              const float bk = win[k >> 2][k & 3];
-              static_for<0, MG>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                const v4f c0 = k == 0 ? (v4f){0.f, 0.f, 0.f, 0.f} : d[q];
-                d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, c0, 4, k & 15, 0);
+            const float *src0 = tile + wrow * S::STRIDE + 4 * xb;
+            auto fetch = [&](int b, v4f(&win)[S::NW], float(&hv)[MG][S::NC]) {
+#pragma unroll
+              for (int u = 0; u < S::NW; ++u) win[u] = *(const v4f *)(src0 + b * S::STRIDE + 4 * u);
+#pragma unroll
+              for (int q = 0; q < MG; ++q)
+#pragma unroll
+                for (int c = 0; c < S::NC; ++c) hv[q][c] = hbase[q][b * hstep[q] + 16 * c];
+            };
+            auto row = [&](const v4f(&win)[S::NW], const float(&hv)[MG][S::NC]) {
+              v4f d[MG];
+              static_for<0, S::KS>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const float bk = win[k >> 2][k & 3];
+                static_for<0, MG>([&](auto qc) {
+                  constexpr int q = decltype(qc)::value;
+                  const v4f c0 = k == 0 ? (v4f){0.f, 0.f, 0.f, 0.f} : d[q];
+                  d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, c0, 4, k & 15, 0);
+                });
               });
-            });
+#pragma unroll
+              for (int q = 0; q < MG; ++q) acc[q] += d[q];
+            };
+            for (int b = b_lo; b <= b_hi; ++b) {
+              v4f win[S::NW];
+              float hv[MG][S::NC];
+              fetch(b, win, hv);
+              row(win, hv);
+            }
           } else {
+           for (int b = b_lo; b <= b_hi; ++b) {
+            v4f d[MG];
             // A operand: lane 4s+i holds Hc_row[4c + k' - i], k' = 0..3, chunk c = 16r + s
             v4s ahi[MG][S::NCB], alo[MG][S::NCB];
 #pragma unroll
             for (int q = 0; q < MG; ++q) {
-              const float *hrow = ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane + b * S::HS + 3 - jj;
+              const float *hrow = (live[q] ? ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane + b * S::HS : zrow) + 3 - jj;
 #pragma unroll
               for (int r = 0; r < S::NCB; ++r) {
-                const int c = 16 * r + bb;
-                v4f hv4 = (v4f){0.f, 0.f, 0.f, 0.f};
-                if (live[q] && c < S::NW) {
-                  const float *p4 = hrow + 4 * c;
-                  hv4 = (v4f){p4[0], p4[1], p4[2], p4[3]};
-                }
+                // chunks past the last are never broadcast: load the last one
+                const int c = min(16 * r + bb, S::NW - 1);
+                const float *p4 = hrow + 4 * c;
+                const v4f hv4 = (v4f){p4[0], p4[1], p4[2], p4[3]};
                 if constexpr (PREC == PREC_SPLIT_)
                   split_bf16(hv4, ahi[q][r], alo[q][r]);
                 else
@@ -280,9 +298,10 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
                 }
               });
             });
-          }
 #pragma unroll
-          for (int q = 0; q < MG; ++q) acc[q] += d[q];
+            for (int q = 0; q < MG; ++q) acc[q] += d[q];
+           }
+          }
         }
       }
 
@@ -351,6 +370,7 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
   float *tile0 = lds;
   float *tile1 = lds + rows * S.stride;
   float *ring = lds + 2 * rows * S.stride;
+  float *zrow = ring + (MG + 1) * g.ky * S.hs;  // hs zeros: A operand of planes out of reach
   const int hplane = g.ky * S.hs;
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -417,6 +437,7 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
       load_h(a);
       store_h(a);
     }
+    for (int e = tid; e < S.hs; e += MT) zrow[e] = 0.f;
     __syncthreads();
     const int b_lo = max(0, g.offy - y0 - 4 * w - 3);
     const int b_hi = min(g.ky - 1, g.iy - 1 + g.offy - y0 - 4 * w);
@@ -431,13 +452,15 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
       if (new_h) load_h(a_new);
 
       if (wave_live) {
+        // A operand rows of plane q, or the zero row when q is not reached
         const float *hbase[MG];
-        bool live[MG];
+        int hstep[MG];
 #pragma unroll
         for (int q = 0; q < MG; ++q) {
           const int aq = zin - z0 - q + g.offz;
-          live[q] = aq >= 0 && aq < g.kz && z0 + q < g.oz;
-          hbase[q] = ring + ((aq + MG + 1) % (MG + 1)) * hplane + 3 + bb - jj;
+          const bool live = aq >= 0 && aq < g.kz && z0 + q < g.oz;
+          hbase[q] = (live ? ring + ((aq + MG + 1) % (MG + 1)) * hplane : zrow) + 3 + bb - jj;
+          hstep[q] = live ? S.hs : 0;
         }
         for (int b = b_lo; b <= b_hi; ++b) {
           const float *src = tile + (4 * w + jj + b) * S.stride + 4 * bb;
@@ -447,7 +470,7 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
           for (int gi = 0; gi < S.nc; ++gi) {
             float hv[MG];
 #pragma unroll
-            for (int q = 0; q < MG; ++q) hv[q] = live[q] ? hbase[q][b * S.hs + 16 * gi] : 0.f;
+            for (int q = 0; q < MG; ++q) hv[q] = hbase[q][b * hstep[q] + 16 * gi];
             static_for<0, 4>([&](auto sc) {
               constexpr int sub = decltype(sc)::value;
               if (4 * gi + sub < S.nw) {
