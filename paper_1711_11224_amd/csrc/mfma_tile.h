@@ -23,7 +23,8 @@
 // wave w owns rows 4w..4w+3 of every plane.  Input planes stream through a
 // double-buffered LDS tile; each staged plane feeds the G output planes it
 // reaches through G different PSF planes, held in an LDS ring of G+1 planes.
-// Partial sums are blocked per PSF row into FP32 accumulators.
+// Partial sums are blocked into FP32 accumulators: per input plane (all
+// PSF rows of that plane) for FP32, per PSF row for the bf16 forms.
 
 #include <type_traits>
 
@@ -71,7 +72,7 @@ struct MfmaShape {
   static constexpr int NW = (KS + 3) / 4;         // float4 input windows per lane (= bf16 chunks)
   static constexpr int NCB = (NW + 15) / 16;      // bf16: broadcast A registers per row
   static constexpr int TCOLS = 4 * XB - 4 + 4 * NW;               // staged input columns
-  static constexpr int STRIDE = ((TCOLS + 23) / 32) * 32 + 8;     // = 8 mod 32 floats
+  static constexpr int STRIDE = ((TCOLS + 15) / 32) * 32 + 16;    // = 16 mod 32 floats
   static constexpr int HS = 16 * NC + 4;          // LDS PSF row stride (>= 4*NW + 3)
   // bf16 input tiles: row stride in bf16 elements, = 16 mod 64 so the 8-byte
   // window reads of 16 lanes (4 rows x 4 x-blocks) hit distinct bank pairs
@@ -234,32 +235,41 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
             const float *src0 = tile + wrow * S::STRIDE + 4 * xb;
             auto fetch = [&](int b, v4f(&win)[S::NW], float(&hv)[MG][S::NC]) {
 #pragma unroll
-              for (int u = 0; u < S::NW; ++u) win[u] = *(const v4f *)(src0 + b * S::STRIDE + 4 * u);
-#pragma unroll
               for (int q = 0; q < MG; ++q)
 #pragma unroll
                 for (int c = 0; c < S::NC; ++c) hv[q][c] = hbase[q][b * hstep[q] + 16 * c];
+#pragma unroll
+              for (int u = 0; u < S::KS / 4; ++u) win[u] = *(const v4f *)(src0 + b * S::STRIDE + 4 * u);
+              // only the steps that exist: no load into registers left unused
+              if constexpr (S::KS % 4 != 0) {
+#pragma unroll
+                for (int e = 0; e < S::KS % 4; ++e) win[S::NW - 1][e] = src0[b * S::STRIDE + 4 * (S::NW - 1) + e];
+              }
             };
-            auto row = [&](const v4f(&win)[S::NW], const float(&hv)[MG][S::NC]) {
-              v4f d[MG];
+            // d: FP32 block sum of this input plane's contribution (all PSF
+            // rows), added to the output accumulators once per plane
+            v4f d[MG];
+#pragma unroll
+            for (int q = 0; q < MG; ++q) d[q] = (v4f){0.f, 0.f, 0.f, 0.f};
+            for (int b = b_lo; b <= b_hi; ++b) {
+              v4f win[S::NW];
+              float hv[MG][S::NC];
+              fetch(b, win, hv);
               static_for<0, S::KS>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 const float bk = win[k >> 2][k & 3];
                 static_for<0, MG>([&](auto qc) {
                   constexpr int q = decltype(qc)::value;
-                  const v4f c0 = k == 0 ? (v4f){0.f, 0.f, 0.f, 0.f} : d[q];
-                  d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, c0, 4, k & 15, 0);
+                  d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, d[q], 4, k & 15, 0);
                 });
               });
-#pragma unroll
-              for (int q = 0; q < MG; ++q) acc[q] += d[q];
-            };
-            for (int b = b_lo; b <= b_hi; ++b) {
-              v4f win[S::NW];
-              float hv[MG][S::NC];
-              fetch(b, win, hv);
-              row(win, hv);
+              // issue order: every LDS read of the row first, so each matrix
+              // instruction waits only for its own operands
+              __builtin_amdgcn_sched_group_barrier(0x100, S::NW + MG * S::NC, 0);
+              __builtin_amdgcn_sched_group_barrier(0x008, S::KS * MG, 0);
             }
+#pragma unroll
+            for (int q = 0; q < MG; ++q) acc[q] += d[q];
           } else {
            for (int b = b_lo; b <= b_hi; ++b) {
             v4f d[MG];
@@ -356,7 +366,7 @@ struct RtShape {
     nw = (ks + 3) / 4;
     nc = (ks + 15) / 16;
     tcols = 60 + 4 * nw;
-    stride = ((tcols + 23) / 32) * 32 + 8;
+    stride = ((tcols + 15) / 32) * 32 + 16;
     hs = 16 * nc + 4;
   }
 };
@@ -462,11 +472,12 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
           hbase[q] = (live ? ring + ((aq + MG + 1) % (MG + 1)) * hplane : zrow) + 3 + bb - jj;
           hstep[q] = live ? S.hs : 0;
         }
+        // d: FP32 block sum of this input plane (all PSF rows)
+        v4f d[MG];
+#pragma unroll
+        for (int q = 0; q < MG; ++q) d[q] = (v4f){0.f, 0.f, 0.f, 0.f};
         for (int b = b_lo; b <= b_hi; ++b) {
           const float *src = tile + (4 * w + jj + b) * S.stride + 4 * bb;
-          v4f d[MG];
-#pragma unroll
-          for (int q = 0; q < MG; ++q) d[q] = (v4f){0.f, 0.f, 0.f, 0.f};
           for (int gi = 0; gi < S.nc; ++gi) {
             float hv[MG];
 #pragma unroll
@@ -485,9 +496,9 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
               }
             });
           }
-#pragma unroll
-          for (int q = 0; q < MG; ++q) acc[q] += d[q];
         }
+#pragma unroll
+        for (int q = 0; q < MG; ++q) acc[q] += d[q];
       }
       if (more) store_plane(((zin + 1 - r_lo) & 1) ? tile1 : tile0);
       if (new_h) store_h(a_new);
