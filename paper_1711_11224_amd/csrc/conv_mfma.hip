@@ -25,8 +25,11 @@ __global__ __launch_bounds__(MT, 2) void conv_mfma_kernel(const float *__restric
 // they pad the output's x extent less than 64-column ones, and for the bf16
 // forms (measured faster at every workload size); otherwise 64 columns.
 int choose_xb(const Geom &g, int precision) {
-  const int w16 = (g.ox + 63) / 64 * 64 - g.ox, w8 = (g.ox + 31) / 32 * 32 - g.ox;
-  return (w8 < w16 || precision != NDC_PREC_NATIVE) ? 8 : 16;
+  // the 32 x 32 tile (two row sets of operands in flight) unless the
+  // 16-row x 64-column tile covers the output plane with less padding
+  const int64_t a8 = (int64_t)((g.ox + 31) / 32) * ((g.oy + 31) / 32);
+  const int64_t a16 = (int64_t)((g.ox + 63) / 64) * ((g.oy + 15) / 16);
+  return (a8 <= a16 || precision != NDC_PREC_NATIVE) ? 8 : 16;
 }
 
 dim3 tile_counts(const Geom &g, int xb) {

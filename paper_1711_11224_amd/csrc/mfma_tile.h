@@ -69,6 +69,7 @@ template <int KX, int XB = 16>
 struct MfmaShape {
   static constexpr int KS = KX + 3;               // unit steps per PSF row
   static constexpr int NC = (KS + 15) / 16;       // FP32: broadcast A registers per row
+  static_assert(NC <= 4, "A operands of a row are held in one float4 per plane");
   static constexpr int NW = (KS + 3) / 4;         // float4 input windows per lane (= bf16 chunks)
   static constexpr int NCB = (NW + 15) / 16;      // bf16: broadcast A registers per row
   static constexpr int TCOLS = 4 * XB - 4 + 4 * NW;               // staged input columns
@@ -233,7 +234,7 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
               hstep[q] = live[q] ? S::HS : 0;
             }
             const float *src0 = tile + wrow * S::STRIDE + 4 * xb;
-            auto fetch = [&](int b, v4f(&win)[S::NW], float(&hv)[MG][S::NC]) {
+            auto fetch = [&](int b, v4f(&win)[S::NW], v4f(&hv)[MG]) {
 #pragma unroll
               for (int q = 0; q < MG; ++q)
 #pragma unroll
@@ -251,10 +252,7 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
             v4f d[MG];
 #pragma unroll
             for (int q = 0; q < MG; ++q) d[q] = (v4f){0.f, 0.f, 0.f, 0.f};
-            for (int b = b_lo; b <= b_hi; ++b) {
-              v4f win[S::NW];
-              float hv[MG][S::NC];
-              fetch(b, win, hv);
+            auto mm = [&](const v4f(&win)[S::NW], const v4f(&hv)[MG]) {
               static_for<0, S::KS>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 const float bk = win[k >> 2][k & 3];
@@ -263,10 +261,42 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
                   d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, d[q], 4, k & 15, 0);
                 });
               });
-              // issue order: every LDS read of the row first, so each matrix
-              // instruction waits only for its own operands
-              __builtin_amdgcn_sched_group_barrier(0x100, S::NW + MG * S::NC, 0);
-              __builtin_amdgcn_sched_group_barrier(0x008, S::KS * MG, 0);
+            };
+            // The next row's LDS reads are spread through this row's matrix
+            // instructions (two register sets, rows alternate between them).
+            constexpr int NDS = S::NW + MG * S::NC, NMM = S::KS * MG;
+            auto interleave = [&]() {
+              static_for<0, NDS>([&](auto) {
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMM / NDS, 0);
+              });
+              __builtin_amdgcn_sched_group_barrier(0x008, NMM, 0);
+            };
+            if constexpr (XB != 8) {
+              // one register set (the 16-block-wide tile has no registers
+              // for two): the row's reads are issued ahead of its matrix
+              // instructions
+              for (int b = b_lo; b <= b_hi; ++b) {
+                v4f win[S::NW], hv[MG];
+                fetch(b, win, hv);
+                mm(win, hv);
+                __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMM, 0);
+              }
+            } else if (b_lo <= b_hi) {
+              v4f w0[S::NW], w1[S::NW];
+              v4f h0[MG], h1[MG];  // A operands of one row: [q][c] (NC <= 4)
+              fetch(b_lo, w0, h0);
+              for (int b = b_lo;; b += 2) {
+                fetch(min(b + 1, b_hi), w1, h1);  // past the end: row b_hi again, unused
+                mm(w0, h0);
+                interleave();
+                if (b + 1 > b_hi) break;
+                fetch(min(b + 2, b_hi), w0, h0);
+                mm(w1, h1);
+                interleave();
+                if (b + 2 > b_hi) break;
+              }
             }
 #pragma unroll
             for (int q = 0; q < MG; ++q) acc[q] += d[q];
