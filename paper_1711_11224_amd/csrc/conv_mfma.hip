@@ -58,8 +58,12 @@ hipError_t launch_kx_xb(const Geom &g, const void *in, const void *H, void *out,
 
 template <int KX, int PREC>
 hipError_t launch_kx(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
-  if (choose_xb(g, PREC) == 8) return launch_kx_xb<KX, PREC, 8>(g, in, H, out, ep, s);
-  return launch_kx_xb<KX, PREC, 16>(g, in, H, out, ep, s);
+  if constexpr (PREC != PREC_NATIVE_) {
+    return launch_kx_xb<KX, PREC, 8>(g, in, H, out, ep, s);  // bf16 forms: 32 x 32 tile only
+  } else {
+    if (choose_xb(g, PREC) == 8) return launch_kx_xb<KX, PREC, 8>(g, in, H, out, ep, s);
+    return launch_kx_xb<KX, PREC, 16>(g, in, H, out, ep, s);
+  }
 }
 
 template <int PREC>

@@ -23,8 +23,8 @@
 // wave w owns rows 4w..4w+3 of every plane.  Input planes stream through a
 // double-buffered LDS tile; each staged plane feeds the G output planes it
 // reaches through G different PSF planes, held in an LDS ring of G+1 planes.
-// Partial sums are blocked into FP32 accumulators: per input plane (all
-// PSF rows of that plane) for FP32, per PSF row for the bf16 forms.
+// Partial sums are blocked into FP32 accumulators per input plane (all PSF
+// rows of that plane), then added to the output accumulators.
 
 #include <type_traits>
 
@@ -301,46 +301,101 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
 #pragma unroll
             for (int q = 0; q < MG; ++q) acc[q] += d[q];
           } else {
-           for (int b = b_lo; b <= b_hi; ++b) {
-            v4f d[MG];
-            // A operand: lane 4s+i holds Hc_row[4c + k' - i], k' = 0..3, chunk c = 16r + s
-            v4s ahi[MG][S::NCB], alo[MG][S::NCB];
+            static_assert(S::NCB == 1, "bf16 A operands: one broadcast register per row");
+            constexpr bool SPLIT = PREC == PREC_SPLIT_;
+            constexpr int NL = SPLIT ? S::NW : 1;
+            // A operand: lane 4s+i holds Hc_row[4s + k' - i], k' = 0..3 (chunk s;
+            // chunks past the last are never broadcast, those lanes load the
+            // last one); the zero row when output plane q is not reached
+            const int ca = 4 * min(bb, S::NW - 1) + 3 - jj;
+            const float *hb[MG];
+            int hst[MG];
 #pragma unroll
             for (int q = 0; q < MG; ++q) {
-              const float *hrow = (live[q] ? ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane + b * S::HS : zrow) + 3 - jj;
+              hb[q] = (live[q] ? ring + ((aq[q] + MG + 1) % (MG + 1)) * hplane : zrow) + ca;
+              hst[q] = live[q] ? S::HS : 0;
+            }
+            const short *srcb0 = (const short *)tile + wrow * S::STRIDE_B + 4 * xb;
+            auto fetch = [&](int b, v4s(&bh)[S::NW], v4s(&bl)[NL], v4f(&av)[MG]) {
 #pragma unroll
-              for (int r = 0; r < S::NCB; ++r) {
-                // chunks past the last are never broadcast: load the last one
-                const int c = min(16 * r + bb, S::NW - 1);
-                const float *p4 = hrow + 4 * c;
-                const v4f hv4 = (v4f){p4[0], p4[1], p4[2], p4[3]};
-                if constexpr (PREC == PREC_SPLIT_)
-                  split_bf16(hv4, ahi[q][r], alo[q][r]);
+              for (int q = 0; q < MG; ++q) {
+                const float *p4 = hb[q] + b * hst[q];
+                av[q] = (v4f){p4[0], p4[1], p4[2], p4[3]};
+              }
+#pragma unroll
+              for (int c = 0; c < S::NW; ++c) bh[c] = *(const v4s *)(srcb0 + b * S::STRIDE_B + 4 * c);
+              if constexpr (SPLIT) {
+#pragma unroll
+                for (int c = 0; c < S::NW; ++c) bl[c] = *(const v4s *)(srcb0 + lo_off + b * S::STRIDE_B + 4 * c);
+              }
+            };
+            // d: FP32 block sum of this input plane (all PSF rows)
+            v4f d[MG];
+#pragma unroll
+            for (int q = 0; q < MG; ++q) d[q] = (v4f){0.f, 0.f, 0.f, 0.f};
+            auto mm = [&](const v4s(&bh)[S::NW], const v4s(&bl)[NL], const v4f(&av)[MG]) {
+              v4s ahi[MG], alo[MG];
+#pragma unroll
+              for (int q = 0; q < MG; ++q) {
+                if constexpr (SPLIT)
+                  split_bf16(av[q], ahi[q], alo[q]);
                 else
-                  ahi[q][r] = to_bf16(hv4);
+                  ahi[q] = to_bf16(av[q]);
+              }
+              static_for<0, S::NW>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                static_for<0, MG>([&](auto qc) {
+                  constexpr int q = decltype(qc)::value;
+                  if constexpr (SPLIT) {
+                    v4f t = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(alo[q], bh[c], d[q], 4, c, 0);
+                    t = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q], bl[c], t, 4, c, 0);
+                    d[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q], bh[c], t, 4, c, 0);
+                  } else {
+                    d[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q], bh[c], d[q], 4, c, 0);
+                  }
+                });
+              });
+            };
+            constexpr int NDS = 4 * MG + S::NW * (SPLIT ? 2 : 1), NMM = S::NW * MG * (SPLIT ? 3 : 1);
+            if constexpr (XB != 8 || SPLIT) {
+              // one register set (split-bf16 has three times the instructions
+              // per row to cover the reads): reads issued ahead of the row
+              for (int b = b_lo; b <= b_hi; ++b) {
+                v4s bh[S::NW], bl[NL];
+                v4f av[MG];
+                fetch(b, bh, bl, av);
+                mm(bh, bl, av);
+                __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 8 * MG, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, NMM, 0);
+              }
+            } else if (b_lo <= b_hi) {
+              // the next row's LDS reads are spread through this row's
+              // matrix instructions (two register sets)
+              auto interleave = [&]() {
+                __builtin_amdgcn_sched_group_barrier(0x002, 8 * MG, 0);
+                static_for<0, NDS>([&](auto) {
+                  __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                  __builtin_amdgcn_sched_group_barrier(0x008, (NMM + NDS - 1) / NDS, 0);
+                });
+                __builtin_amdgcn_sched_group_barrier(0x008, NMM, 0);
+              };
+              v4s bh0[S::NW], bl0[NL], bh1[S::NW], bl1[NL];
+              v4f av0[MG], av1[MG];
+              fetch(b_lo, bh0, bl0, av0);
+              for (int b = b_lo;; b += 2) {
+                fetch(min(b + 1, b_hi), bh1, bl1, av1);  // past the end: row b_hi again, unused
+                mm(bh0, bl0, av0);
+                interleave();
+                if (b + 1 > b_hi) break;
+                fetch(min(b + 2, b_hi), bh0, bl0, av0);
+                mm(bh1, bl1, av1);
+                interleave();
+                if (b + 2 > b_hi) break;
               }
             }
-            const short *srcb = (const short *)tile + (wrow + b) * S::STRIDE_B + 4 * xb;
-            static_for<0, S::NW>([&](auto cc) {
-              constexpr int c = decltype(cc)::value;
-              const v4s bhi = *(const v4s *)(srcb + 4 * c);
-              v4s blo;
-              if constexpr (PREC == PREC_SPLIT_) blo = *(const v4s *)(srcb + lo_off + 4 * c);
-              static_for<0, MG>([&](auto qc) {
-                constexpr int q = decltype(qc)::value;
-                const v4f c0 = c == 0 ? (v4f){0.f, 0.f, 0.f, 0.f} : d[q];
-                if constexpr (PREC == PREC_SPLIT_) {
-                  v4f t = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(alo[q][c >> 4], bhi, c0, 4, c & 15, 0);
-                  t = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q][c >> 4], blo, t, 4, c & 15, 0);
-                  d[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q][c >> 4], bhi, t, 4, c & 15, 0);
-                } else {
-                  d[q] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ahi[q][c >> 4], bhi, c0, 4, c & 15, 0);
-                }
-              });
-            });
 #pragma unroll
             for (int q = 0; q < MG; ++q) acc[q] += d[q];
-           }
           }
         }
       }
