@@ -3,65 +3,74 @@
 //
 // out[s] = sum_t Hc[t] in[s + t - off]  (see Geom), FP32 or FP64.
 //
-// A work-group owns an 8-row x 128-column column of the output and walks it
+// A work-group owns a 16-row x 64-column column of the output and walks it
 // along z, reading every input plane of its column from HBM once:
 //   * the next input plane is prefetched into registers while the current
 //     one (double-buffered in LDS) is consumed;
-//   * each thread keeps 4 consecutive x outputs; for every tap row b it loads
-//     a (4 + kx - 1)-wide window once and applies it to all kz output planes
-//     the input plane reaches (kz x kx x 4 FMAs per window);
-//   * per-output partial sums of each input plane are added to a ring of kz
-//     accumulator planes in LDS that only the owning thread touches, and an
-//     output plane is finished (fused epilogue) when its last input plane has
-//     been added.
+//   * each thread keeps 4 consecutive x outputs of one row; for every tap row
+//     b it loads a (4 + kx - 1)-wide window once and applies it to all kz
+//     output planes the input plane reaches (kz x kx x 4 FMAs per window);
+//   * the kz output planes in flight are register accumulators: the z walk
+//     is unrolled kz times with its phase fixed so that output plane z always
+//     lands in accumulator z mod kz, a compile-time index.  A plane is
+//     finished (fused epilogue) when its last input plane has been added.
 // Taps live in LDS (rows padded to 8) and are read as uniform float4.
 #include "ndc_device.h"
 #include "ndc_internal.h"
+
+#include <type_traits>
 
 namespace ndc {
 namespace {
 
 constexpr int ST = 256;          // threads
 constexpr int SRX = 4;           // x outputs per thread
-constexpr int STX = 32 * SRX;    // 128 output columns
-constexpr int STY = ST / 32;     // 8 output rows
+constexpr int STX = 16 * SRX;    // 64 output columns
+constexpr int STY = ST / 16;     // 16 output rows
 constexpr int SMAXK = 7;         // max taps per axis
 constexpr int SZC = 32;          // output planes per work-group
-constexpr int SCOLS = STX + SMAXK - 1;              // staged columns (134)
-constexpr int SSTRIDE = (SCOLS + 3) / 4 * 4 + 4;    // 140
-constexpr int SROWS = STY + SMAXK - 1;              // 14
+constexpr int SCOLS = STX + SMAXK - 1;              // staged columns (70)
+constexpr int SSTRIDE = (SCOLS + 3) / 4 * 4 + 4;    // 76
+constexpr int SROWS = STY + SMAXK - 1;              // 22
 constexpr int SPLANE = SROWS * SSTRIDE;
 constexpr int SNIN = (SROWS * SCOLS + ST - 1) / ST; // staging registers per thread
 
-template <typename T>
-__host__ __device__ constexpr size_t small_lds_bytes(int kz) {
-  // two input planes, kz accumulator planes (4 x 256 values), taps (kz*7 rows of 8)
-  return sizeof(T) * ((size_t)2 * SPLANE + (size_t)kz * SRX * ST + (size_t)SMAXK * SMAXK * 8);
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
 }
 
-template <typename T, int KX>
+template <typename T>
+__host__ __device__ constexpr size_t small_lds_bytes(int kz) {
+  // two input planes, taps (kz*7 rows of 8)
+  return sizeof(T) * ((size_t)2 * SPLANE + (size_t)kz * SMAXK * 8);
+}
+
+template <typename T, int KX, int KZ>
 __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in, const T *__restrict__ H,
                                                         T *__restrict__ out, Geom g, Epi ep, int nbx, int nby) {
   if (ep.phase && !((1 << *ep.phase) & ep.phase_mask)) return;
   extern __shared__ __align__(16) unsigned char small_lds[];
   T *planes = (T *)small_lds;                  // 2 x SPLANE
-  T *accs = planes + 2 * SPLANE;               // kz x SRX x ST (thread-private slots)
-  T *taps = accs + (size_t)g.kz * SRX * ST;    // [a][b][8]
+  T *taps = planes + 2 * SPLANE;               // [a][b][8]
   __shared__ double red[ST / 64][2];
 
   const int id = blockIdx.x;
   const int tx = id % nbx, ty = (id / nbx) % nby, tz = id / (nbx * nby);
   const int x0 = tx * STX, y0 = ty * STY, zlo = tz * SZC, zhi = min(g.oz, zlo + SZC);
-  const int tid = threadIdx.x, lx = tid % 32, ly = tid / 32;
+  const int tid = threadIdx.x, lx = tid % 16, ly = tid / 16;
   const int rows = STY + g.ky - 1, cols = STX + KX - 1;
   double s0 = 0.0, s1 = 0.0;
 
   // taps, flipped for the forward operator, rows padded with zeros to 8
-  for (int e = tid; e < g.kz * g.ky * 8; e += ST) {
+  for (int e = tid; e < KZ * g.ky * 8; e += ST) {
     const int c = e % 8, ab = e / 8, b = ab % g.ky, a = ab / g.ky;
     T v = (T)0;
     if (c < KX) {
-      const int ha = g.flip ? g.kz - 1 - a : a, hb = g.flip ? g.ky - 1 - b : b, hc = g.flip ? KX - 1 - c : c;
+      const int ha = g.flip ? KZ - 1 - a : a, hb = g.flip ? g.ky - 1 - b : b, hc = g.flip ? KX - 1 - c : c;
       v = H[((int64_t)ha * g.ky + hb) * KX + hc];
     }
     taps[e] = v;
@@ -79,17 +88,16 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
     }
   };
   // input planes of output plane z: [max(0, z-offz), min(iz-1, z-offz+kz-1)]
-  auto first_in = [&](int z) { return max(0, z - g.offz); };
-  auto last_in = [&](int z) { return min(g.iz - 1, z - g.offz + g.kz - 1); };
+  auto last_in = [&](int z) { return min(g.iz - 1, z - g.offz + KZ - 1); };
 
   // output planes that no input plane reaches are zero
   for (int z = zlo; z < zhi; ++z)
-    if (first_in(z) > last_in(z)) {
+    if (max(0, z - g.offz) > last_in(z)) {
       const T zero[SRX] = {};
       emit(z, zero);
     }
 
-  const int r_lo = max(0, zlo - g.offz), r_hi = min(g.iz - 1, zhi - 1 + g.kz - 1 - g.offz);
+  const int r_lo = max(0, zlo - g.offz), r_hi = min(g.iz - 1, zhi - 1 + KZ - 1 - g.offz);
   T inreg[SNIN];
   auto load_plane = [&](int zin) {
 #pragma unroll
@@ -103,63 +111,72 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
       inreg[u] = v;
     }
   };
-  if (r_lo <= r_hi) load_plane(r_lo);
-  for (int zin = r_lo; zin <= r_hi; ++zin) {
-    T *pl = planes + (zin & 1) * SPLANE;
-    __syncthreads();  // the buffer being filled is no longer read; taps are visible
-#pragma unroll
-    for (int u = 0; u < SNIN; ++u) {
-      const int e = tid + u * ST;
-      const int r = e / SCOLS, q = e - r * SCOLS;
-      if (r < SROWS) pl[r * SSTRIDE + q] = inreg[u];
-    }
-    __syncthreads();
-    if (zin < r_hi) load_plane(zin + 1);
 
-    // output plane z_a = zin + offz - a receives tap plane a of this input plane
-    T part[SMAXK][SRX];
-    bool live[SMAXK];
+  // acc[j]: output plane z with (z mod KZ) == j (z >= 0, offz >= 0)
+  T acc[KZ][SRX];
 #pragma unroll
-    for (int a = 0; a < SMAXK; ++a) {
-      const int z = zin + g.offz - a;
-      live[a] = a < g.kz && z >= zlo && z < zhi;
+  for (int j = 0; j < KZ; ++j)
 #pragma unroll
-      for (int r = 0; r < SRX; ++r) part[a][r] = (T)0;
-    }
-    for (int b = 0; b < g.ky; ++b) {
-      const T *src = pl + (ly + b) * SSTRIDE + lx * SRX;
-      T w[SRX + KX - 1];
+    for (int r = 0; r < SRX; ++r) acc[j][r] = (T)0;
+
+  if (r_lo <= r_hi) load_plane(r_lo);
+  // the walk starts at the input plane zs0 <= r_lo with (zs0 + offz) mod KZ
+  // == 0, so input plane zs0 + u reaches output plane z = zs0 + u + offz - a
+  // through tap plane a, and z mod KZ == (u - a) mod KZ
+  const int zs0 = r_lo - (r_lo + g.offz) % KZ;
+  for (int zs = zs0; zs <= r_hi; zs += KZ) {
+    sfor<0, KZ>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const int zin = zs + u;
+      if (zin < r_lo || zin > r_hi) return;  // uniform
+      T *pl = planes + ((zin - r_lo) & 1) * SPLANE;
+      __syncthreads();  // the buffer being filled is no longer read; taps are visible
 #pragma unroll
-      for (int u = 0; u < SRX + KX - 1; ++u) w[u] = src[u];
-#pragma unroll
-      for (int a = 0; a < SMAXK; ++a) {
-        if (live[a]) {
-          const T *hrow = taps + (a * g.ky + b) * 8;
-#pragma unroll
-          for (int c = 0; c < KX; ++c) {
-            const T hv = hrow[c];
-#pragma unroll
-            for (int r = 0; r < SRX; ++r) part[a][r] += hv * w[r + c];
-          }
-        }
+      for (int v = 0; v < SNIN; ++v) {
+        const int e = tid + v * ST;
+        const int r = e / SCOLS, q = e - r * SCOLS;
+        if (r < SROWS) pl[r * SSTRIDE + q] = inreg[v];
       }
-    }
+      __syncthreads();
+      if (zin < r_hi) load_plane(zin + 1);
+
+      bool live[KZ];
 #pragma unroll
-    for (int a = 0; a < SMAXK; ++a) {
-      if (live[a]) {
+      for (int a = 0; a < KZ; ++a) {
         const int z = zin + g.offz - a;
-        T *slot = accs + (size_t)(z % g.kz) * SRX * ST + tid;
-        T acc[SRX];
-#pragma unroll
-        for (int r = 0; r < SRX; ++r) acc[r] = (zin == first_in(z) ? (T)0 : slot[r * ST]) + part[a][r];
-        if (zin == last_in(z)) {
-          emit(z, acc);
-        } else {
-#pragma unroll
-          for (int r = 0; r < SRX; ++r) slot[r * ST] = acc[r];
-        }
+        live[a] = z >= zlo && z < zhi;
       }
-    }
+      for (int b = 0; b < g.ky; ++b) {
+        const T *src = pl + (ly + b) * SSTRIDE + lx * SRX;
+        T w[SRX + KX - 1];
+#pragma unroll
+        for (int e = 0; e < SRX + KX - 1; ++e) w[e] = src[e];
+        sfor<0, KZ>([&](auto ac) {
+          constexpr int a = decltype(ac)::value;
+          constexpr int j = ((u - a) % KZ + KZ) % KZ;
+          if (live[a]) {
+            const T *hrow = taps + (a * g.ky + b) * 8;
+#pragma unroll
+            for (int c = 0; c < KX; ++c) {
+              const T hv = hrow[c];
+#pragma unroll
+              for (int r = 0; r < SRX; ++r) acc[j][r] += hv * w[r + c];
+            }
+          }
+        });
+      }
+      // output planes completed by this input plane
+      sfor<0, KZ>([&](auto ac) {
+        constexpr int a = decltype(ac)::value;
+        constexpr int j = ((u - a) % KZ + KZ) % KZ;
+        const int z = zin + g.offz - a;
+        if (live[a] && zin == last_in(z)) {
+          emit(z, acc[j]);
+#pragma unroll
+          for (int r = 0; r < SRX; ++r) acc[j][r] = (T)0;
+        }
+      });
+    });
   }
 
   if (ep.mode != EPI_STORE) {
@@ -171,21 +188,32 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
   }
 }
 
-template <typename T, int KX>
+template <typename T, int KX, int KZ>
 hipError_t launch_small_t(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
   const int nbx = (g.ox + STX - 1) / STX, nby = (g.oy + STY - 1) / STY, nbz = (g.oz + SZC - 1) / SZC;
-  hipLaunchKernelGGL((conv_small_kernel<T, KX>), dim3(nbx * nby * nbz), dim3(ST), small_lds_bytes<T>(g.kz), s,
+  hipLaunchKernelGGL((conv_small_kernel<T, KX, KZ>), dim3(nbx * nby * nbz), dim3(ST), small_lds_bytes<T>(KZ), s,
                      (const T *)in, (const T *)H, (T *)out, g, ep, nbx, nby);
   return hipGetLastError();
 }
 
+template <typename T, int KZ>
+hipError_t launch_small_kz(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
+  switch (g.kx) {
+    case 1: return launch_small_t<T, 1, KZ>(g, in, H, out, ep, s);
+    case 3: return launch_small_t<T, 3, KZ>(g, in, H, out, ep, s);
+    case 5: return launch_small_t<T, 5, KZ>(g, in, H, out, ep, s);
+    case 7: return launch_small_t<T, 7, KZ>(g, in, H, out, ep, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 hipError_t launch_small_dt(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
-  switch (g.kx) {
-    case 1: return launch_small_t<T, 1>(g, in, H, out, ep, s);
-    case 3: return launch_small_t<T, 3>(g, in, H, out, ep, s);
-    case 5: return launch_small_t<T, 5>(g, in, H, out, ep, s);
-    case 7: return launch_small_t<T, 7>(g, in, H, out, ep, s);
+  switch (g.kz) {
+    case 1: return launch_small_kz<T, 1>(g, in, H, out, ep, s);
+    case 3: return launch_small_kz<T, 3>(g, in, H, out, ep, s);
+    case 5: return launch_small_kz<T, 5>(g, in, H, out, ep, s);
+    case 7: return launch_small_kz<T, 7>(g, in, H, out, ep, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -194,7 +222,8 @@ hipError_t launch_small_dt(const Geom &g, const void *in, const void *H, void *o
 
 bool small_supported(const Geom &g, int dtype, int precision) {
   if (precision != NDC_PREC_NATIVE) return false;
-  if (g.kx > SMAXK || g.ky > SMAXK || g.kz > SMAXK || !(g.kx & 1)) return false;
+  if (g.kx > SMAXK || g.ky > SMAXK || g.kz > SMAXK || !(g.kx & 1) || !(g.kz & 1)) return false;
+  if (g.offz < 0) return false;
   const size_t bytes = dtype == NDC_F64 ? small_lds_bytes<double>(g.kz) : small_lds_bytes<float>(g.kz);
   return bytes <= 64 * 1024;
 }

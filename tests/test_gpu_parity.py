@@ -49,6 +49,13 @@ CASES = [
     ((70,), (5,)),
     ((33, 47), (4, 6)),
     ((7, 19, 150), (3, 9, 15)),
+    # every axis <= 7 taps (the streaming small-PSF kernel): several 16 x 64
+    # tiles and 32-plane z blocks with ragged tails, 2p >= m, kz = 1, 2-D
+    ((40, 37, 150), (3, 3, 3)),
+    ((9, 70, 65), (1, 2, 1)),
+    ((3, 5, 200), (2, 1, 3)),
+    ((70, 20, 20), (0, 3, 1)),
+    ((100, 130), (3, 2)),
 ]
 
 
