@@ -76,15 +76,14 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
     taps[e] = v;
   }
 
+  const int yo = y0 + ly, xo = x0 + lx * SRX;
+  const int64_t ostride = (int64_t)g.oy * g.ox, orow = (int64_t)yo * g.ox + xo;
   auto emit = [&](int z, const T *acc) {  // finished output plane z
-    const int y = y0 + ly;
-    if (y < g.oy) {
-      const int64_t rowbase = ((int64_t)z * g.oy + y) * g.ox;
+    if (yo < g.oy) {
+      const int64_t base = z * ostride + orow;
 #pragma unroll
-      for (int r = 0; r < SRX; ++r) {
-        const int x = x0 + lx * SRX + r;
-        if (x < g.ox) apply_epilogue<T>(out, rowbase + x, acc[r], ep, s0, s1);
-      }
+      for (int r = 0; r < SRX; ++r)
+        if (xo + r < g.ox) apply_epilogue<T>(out, base + r, acc[r], ep, s0, s1);
     }
   };
   // input planes of output plane z: [max(0, z-offz), min(iz-1, z-offz+kz-1)]
@@ -98,18 +97,31 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
     }
 
   const int r_lo = max(0, zlo - g.offz), r_hi = min(g.iz - 1, zhi - 1 + KZ - 1 - g.offz);
+  // staging element u of this thread: offset inside an input plane (-1:
+  // outside the input, staged as zero) and LDS offset inside a plane buffer
+  // (-1: past the staged rows); both are the same for every plane
+  // (the plane offset is clamped into the plane and a validity bit kept)
+  unsigned goff[SNIN], gvalid = 0;
+  int loff[SNIN];
+#pragma unroll
+  for (int u = 0; u < SNIN; ++u) {
+    const int e = tid + u * ST;
+    const int r = e / SCOLS, q = e - r * SCOLS;
+    const int yin = y0 + r - g.offy, xin = x0 + q - g.offx;
+    const bool ok = r < rows && q < cols && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix;
+    goff[u] = ok ? (unsigned)(yin * g.ix + xin) : 0u;
+    gvalid |= ok ? 1u << u : 0u;
+    loff[u] = r < SROWS ? r * SSTRIDE + q : -1;
+  }
+  const int64_t pstride = (int64_t)g.iy * g.ix;
   T inreg[SNIN];
   auto load_plane = [&](int zin) {
+    // uniform plane base + 32-bit per-thread offsets (always inside the
+    // plane); elements outside the input are zeroed when staged, so nothing
+    // waits for these loads before the plane's compute
+    const T *plane = in + zin * pstride;
 #pragma unroll
-    for (int u = 0; u < SNIN; ++u) {
-      const int e = tid + u * ST;
-      const int r = e / SCOLS, q = e - r * SCOLS;
-      const int yin = y0 + r - g.offy, xin = x0 + q - g.offx;
-      T v = (T)0;
-      if (r < rows && q < cols && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix)
-        v = in[((int64_t)zin * g.iy + yin) * g.ix + xin];
-      inreg[u] = v;
-    }
+    for (int u = 0; u < SNIN; ++u) inreg[u] = plane[goff[u]];
   };
 
   // acc[j]: output plane z with (z mod KZ) == j (z >= 0, offz >= 0)
@@ -119,6 +131,8 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
 #pragma unroll
     for (int r = 0; r < SRX; ++r) acc[j][r] = (T)0;
 
+  T done[SRX];  // finished output plane pz (-1: none) not yet stored
+  int pz = -1;
   if (r_lo <= r_hi) load_plane(r_lo);
   // the walk starts at the input plane zs0 <= r_lo with (zs0 + offz) mod KZ
   // == 0, so input plane zs0 + u reaches output plane z = zs0 + u + offz - a
@@ -132,13 +146,17 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
       T *pl = planes + ((zin - r_lo) & 1) * SPLANE;
       __syncthreads();  // the buffer being filled is no longer read; taps are visible
 #pragma unroll
-      for (int v = 0; v < SNIN; ++v) {
-        const int e = tid + v * ST;
-        const int r = e / SCOLS, q = e - r * SCOLS;
-        if (r < SROWS) pl[r * SSTRIDE + q] = inreg[v];
-      }
+      for (int v = 0; v < SNIN; ++v)
+        if (loff[v] >= 0) pl[loff[v]] = (gvalid >> v) & 1u ? inreg[v] : (T)0;
       __syncthreads();
+      // the next plane's loads, then the stores of the plane finished one
+      // input plane ago: both are in flight during this plane's compute, and
+      // the wait for those loads at the next staging step finds the stores done
       if (zin < r_hi) load_plane(zin + 1);
+      if (pz >= 0) {
+        emit(pz, done);
+        pz = -1;
+      }
 
       bool live[KZ];
 #pragma unroll
@@ -171,13 +189,22 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
         constexpr int j = ((u - a) % KZ + KZ) % KZ;
         const int z = zin + g.offz - a;
         if (live[a] && zin == last_in(z)) {
-          emit(z, acc[j]);
+          // below the last input plane at most one output plane finishes per
+          // input plane: its values wait in `done` for the next staging step
+          if (zin < g.iz - 1 && zin < r_hi) {
+#pragma unroll
+            for (int r = 0; r < SRX; ++r) done[r] = acc[j][r];
+            pz = z;
+          } else {
+            emit(z, acc[j]);
+          }
 #pragma unroll
           for (int r = 0; r < SRX; ++r) acc[j][r] = (T)0;
         }
       });
     });
   }
+  if (pz >= 0) emit(pz, done);
 
   if (ep.mode != EPI_STORE) {
     block_sum2(s0, s1, red);
@@ -224,6 +251,7 @@ bool small_supported(const Geom &g, int dtype, int precision) {
   if (precision != NDC_PREC_NATIVE) return false;
   if (g.kx > SMAXK || g.ky > SMAXK || g.kz > SMAXK || !(g.kx & 1) || !(g.kz & 1)) return false;
   if (g.offz < 0) return false;
+  if ((int64_t)g.iy * g.ix >= ((int64_t)1 << 31)) return false;  // 31-bit element offsets inside a plane
   const size_t bytes = dtype == NDC_F64 ? small_lds_bytes<double>(g.kz) : small_lds_bytes<float>(g.kz);
   return bytes <= 64 * 1024;
 }
