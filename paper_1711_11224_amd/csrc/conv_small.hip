@@ -5,8 +5,8 @@
 //
 // A work-group owns a 16-row x 64-column column of the output and walks it
 // along z, reading every input plane of its column from HBM once:
-//   * the next input plane is prefetched into registers while the current
-//     one (double-buffered in LDS) is consumed;
+//   * the next input plane is in flight into registers while the current one
+//     (double-buffered in LDS, one barrier per plane) is consumed;
 //   * each thread keeps 4 consecutive x outputs of one row; for every tap row
 //     b it loads a (4 + kx - 1)-wide window once and applies it to all kz
 //     output planes the input plane reaches (kz x kx x 4 FMAs per window);
@@ -133,7 +133,19 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
 
   T done[SRX];  // finished output plane pz (-1: none) not yet stored
   int pz = -1;
-  if (r_lo <= r_hi) load_plane(r_lo);
+  auto stage = [&](int zin) {  // registers -> LDS buffer of plane zin
+    T *pl = planes + ((zin - r_lo) & 1) * SPLANE;
+#pragma unroll
+    for (int v = 0; v < SNIN; ++v)
+      if (loff[v] >= 0) pl[loff[v]] = (gvalid >> v) & 1u ? inreg[v] : (T)0;
+  };
+  // plane r_lo staged, plane r_lo + 1 in flight
+  if (r_lo <= r_hi) {
+    load_plane(r_lo);
+    stage(r_lo);
+    if (r_lo < r_hi) load_plane(r_lo + 1);
+  }
+  __syncthreads();
   // the walk starts at the input plane zs0 <= r_lo with (zs0 + offz) mod KZ
   // == 0, so input plane zs0 + u reaches output plane z = zs0 + u + offz - a
   // through tap plane a, and z mod KZ == (u - a) mod KZ
@@ -143,16 +155,9 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
       constexpr int u = decltype(uc)::value;
       const int zin = zs + u;
       if (zin < r_lo || zin > r_hi) return;  // uniform
-      T *pl = planes + ((zin - r_lo) & 1) * SPLANE;
-      __syncthreads();  // the buffer being filled is no longer read; taps are visible
-#pragma unroll
-      for (int v = 0; v < SNIN; ++v)
-        if (loff[v] >= 0) pl[loff[v]] = (gvalid >> v) & 1u ? inreg[v] : (T)0;
-      __syncthreads();
-      // the next plane's loads, then the stores of the plane finished one
-      // input plane ago: both are in flight during this plane's compute, and
-      // the wait for those loads at the next staging step finds the stores done
-      if (zin < r_hi) load_plane(zin + 1);
+      const T *pl = planes + ((zin - r_lo) & 1) * SPLANE;
+      // stores of the plane finished one input plane ago: in flight during
+      // this plane's compute
       if (pz >= 0) {
         emit(pz, done);
         pz = -1;
@@ -202,6 +207,15 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
           for (int r = 0; r < SRX; ++r) acc[j][r] = (T)0;
         }
       });
+      // Plane zin+1 (loaded during this plane) goes to the other buffer, whose
+      // readers finished before the last barrier; then plane zin+2 is loaded.
+      // One barrier per plane: after it plane zin+1 is staged and nobody
+      // reads plane zin's buffer any more.
+      if (zin < r_hi) {
+        stage(zin + 1);
+        if (zin + 1 < r_hi) load_plane(zin + 2);
+      }
+      __syncthreads();
     });
   }
   if (pz >= 0) emit(pz, done);
