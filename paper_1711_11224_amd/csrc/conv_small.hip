@@ -28,7 +28,7 @@ constexpr int SRX = 4;           // x outputs per thread
 constexpr int STX = 16 * SRX;    // 64 output columns
 constexpr int STY = ST / 16;     // 16 output rows
 constexpr int SMAXK = 7;         // max taps per axis
-constexpr int SZC = 32;          // output planes per work-group
+constexpr int SZC = 16;          // output planes per work-group
 constexpr int SCOLS = STX + SMAXK - 1;              // staged columns (70)
 constexpr int SSTRIDE = (SCOLS + 3) / 4 * 4 + 4;    // 76
 constexpr int SROWS = STY + SMAXK - 1;              // 22
