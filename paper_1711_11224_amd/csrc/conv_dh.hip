@@ -13,6 +13,8 @@
 #include "ndc_device.h"
 #include "ndc_internal.h"
 
+#include <type_traits>
+
 namespace ndc {
 namespace {
 
@@ -120,22 +122,223 @@ size_t dh_lds_bytes(const DhGeom &d, size_t es) {
   return es * ((size_t)DYC * DXC + (size_t)(DYC + d.ky - 1) * d.gstride);
 }
 
+// ---------------------------------------------------------------------------
+// FP32 matrix-core form (v_mfma_f32_4x4x1f32, 16 independent 4x4 blocks).
+//
+// Instruction block k takes the x position x0 + k of a 16-wide chunk; lane
+// 4k+i holds A_k[i] = G[zg, yg, x + c0 + i], lane 4k+j holds
+// B_k[j] = X[zg - a, yg - b0 - j, x], so register i of lane 4k+j gathers
+//   dH[a, b0 + j, c0 + i] += G[zg, yg, x + c0 + i] * X[zg - a, yg - b0 - j, x]
+// for one G row yg: a 4 (b) x 4 (c) tile of one PSF plane per instruction.
+// A wave keeps up to 6 x 6 such tiles (a 24 x 24 block of the PSF plane) in
+// registers, reading 6 G and 6 X values from LDS per 36 instructions.
+//
+// Work-group (a, PSF block, split s): PSF plane a, one block of rows/columns
+// of it, X plane z and a range of G rows (the split).  G and X tiles of
+// 16 G rows x 128 columns (with the X halo of the block's rows) are staged in
+// LDS; wave w takes G rows 4w .. 4w+3 of each tile.  At the end the 16 x
+// blocks and the 4 waves are summed in fixed order and the split's partial
+// PSF block is written; the splits are added in double precision afterwards.
+constexpr int HQY = 16;              // G rows per staged tile
+constexpr int HQX = 128;             // X columns per staged tile
+constexpr int HMT = 6;               // max 4-wide tiles per block along b and c
+constexpr int HXS = HQX + 16;        // X tile row stride (= 16 mod 64: 4 rows x 16 lanes, no bank conflict)
+constexpr int HXR = HQY + 4 * HMT - 1;                  // X tile rows (39)
+constexpr int HGS = HQX + 4 * HMT + 4;                  // G tile row stride (>= 128 + 23 + 1)
+constexpr int HLDS = HXR * HXS + HQY * HGS;             // floats
+constexpr int HTHREADS = 256;
+
+struct DhmGeom {
+  int mz, my, mx, kz, ky, kx, gy, gx;
+  int tb, tc, nbb, nbc;   // tiles per block along b / c, blocks along b / c
+  int nys, ysplit;        // G-row splits per X plane, G rows per split (multiple of HQY)
+  int nsplit;             // mz * nys
+};
+
+DhmGeom dhm_geom(const int64_t m3[3], const int64_t p3[3]) {
+  DhmGeom d;
+  d.mz = (int)m3[0];
+  d.my = (int)m3[1];
+  d.mx = (int)m3[2];
+  d.kz = (int)(2 * p3[0] + 1);
+  d.ky = (int)(2 * p3[1] + 1);
+  d.kx = (int)(2 * p3[2] + 1);
+  d.gy = d.my + d.ky - 1;
+  d.gx = d.mx + d.kx - 1;
+  const int ntb = (d.ky + 3) / 4, ntc = (d.kx + 3) / 4;
+  d.nbb = (ntb + HMT - 1) / HMT;
+  d.nbc = (ntc + HMT - 1) / HMT;
+  d.tb = (ntb + d.nbb - 1) / d.nbb;
+  d.tc = (ntc + d.nbc - 1) / d.nbc;
+  // split G rows only as far as needed to give the chip ~2048 work-groups
+  const int64_t base = (int64_t)d.kz * d.nbb * d.nbc * d.mz;
+  const int ytiles = (d.gy + HQY - 1) / HQY;
+  int64_t want = (2048 + base - 1) / base;
+  if (want > ytiles) want = ytiles;
+  if (want < 1) want = 1;
+  const int per = (int)((ytiles + want - 1) / want);
+  d.ysplit = per * HQY;
+  d.nys = (d.gy + d.ysplit - 1) / d.ysplit;
+  d.nsplit = d.mz * d.nys;
+  return d;
+}
+
+typedef float dh_v4f __attribute__((ext_vector_type(4)));
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void dh_sfor(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    dh_sfor<B + 1, E>(f);
+  }
+}
+
+// T x T tiles per wave (T = the larger of the block's tile counts; tiles past
+// the block are computed and dropped).
+template <int T>
+__global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__restrict__ X, const float *__restrict__ G,
+                                                              float *__restrict__ part, DhmGeom d) {
+  __shared__ __align__(16) float lds[HLDS];
+  __shared__ float red[4][4 * HMT * HMT][4];  // [wave][tile*4 + j][i]
+  float *xt = lds;                 // HXR x HXS
+  float *gt = lds + HXR * HXS;     // HQY x HGS
+  int id = blockIdx.x;
+  const int a = id % d.kz;
+  id /= d.kz;
+  const int bc = id % d.nbc;
+  id /= d.nbc;
+  const int bb = id % d.nbb;
+  const int split = id / d.nbb;
+  const int z = split / d.nys, ys = split - z * d.nys;
+  const int b0 = bb * 4 * d.tb, c0 = bc * 4 * d.tc;
+  constexpr int xrows = HQY + 4 * T - 1;                // X rows staged per tile
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int k = lane >> 2, q4 = lane & 3;               // block (x offset), i or j
+  const float *Xp = X + (int64_t)z * d.my * d.mx;
+  const float *Gp = G + (int64_t)(z + a) * d.gy * d.gx;
+
+  dh_v4f acc[T][T];
+#pragma unroll
+  for (int u = 0; u < T; ++u)
+#pragma unroll
+    for (int v = 0; v < T; ++v) acc[u][v] = (dh_v4f){0.f, 0.f, 0.f, 0.f};
+
+  const int y_lo = ys * d.ysplit, y_hi = min(d.gy, y_lo + d.ysplit);
+  for (int yt = y_lo; yt < y_hi; yt += HQY) {
+    for (int xt0 = 0; xt0 < d.mx; xt0 += HQX) {
+      __syncthreads();  // previous tile no longer read
+      // X rows yt - b0 - 4T + 1 .. yt + 15 - b0, columns xt0 .. xt0 + 127
+      const int xr0 = yt - b0 - 4 * T + 1;
+      for (int e = tid; e < xrows * HQX; e += HTHREADS) {
+        const int r = e / HQX, c = e - r * HQX;
+        const int yx = xr0 + r, xx = xt0 + c;
+        xt[r * HXS + c] = (yx >= 0 && yx < d.my && xx < d.mx) ? Xp[(int64_t)yx * d.mx + xx] : 0.f;
+      }
+      // G rows yt .. yt + 15, columns xt0 + c0 .. xt0 + c0 + HGS - 1
+      for (int e = tid; e < HQY * HGS; e += HTHREADS) {
+        const int r = e / HGS, c = e - r * HGS;
+        const int yg = yt + r, xg = xt0 + c0 + c;
+        gt[e] = (yg < y_hi && xg < d.gx) ? Gp[(int64_t)yg * d.gx + xg] : 0.f;
+      }
+      __syncthreads();
+      const int nch = min(HQX, d.mx - xt0 + 15) / 16;  // 16-wide chunks with any X column
+#pragma unroll 1
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * w + r;  // G row inside the tile
+        if (yt + row >= y_hi) break;
+#pragma unroll 1
+        for (int ch = 0; ch < nch; ++ch) {
+          float av[T], bv[T];
+#pragma unroll
+          for (int v = 0; v < T; ++v) av[v] = gt[row * HGS + 16 * ch + k + 4 * v + q4];
+#pragma unroll
+          for (int u = 0; u < T; ++u)  // X row for b = b0 + 4u + j: tile row row + 4T - 1 - 4u - j (>= 0)
+            bv[u] = xt[(row + 4 * T - 1 - 4 * u - q4) * HXS + 16 * ch + k];
+          dh_sfor<0, T>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            dh_sfor<0, T>([&](auto vc) {
+              constexpr int v = decltype(vc)::value;
+              acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(av[v], bv[u], acc[u][v], 0, 0, 0);
+            });
+          });
+        }
+      }
+    }
+  }
+
+  // sum the 16 x blocks (lanes 4k + j, k = 0..15) in fixed order
+#pragma unroll
+  for (int u = 0; u < T; ++u) {
+#pragma unroll
+    for (int v = 0; v < T; ++v)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float t = acc[u][v][i];
+        t += __shfl_xor(t, 4);
+        t += __shfl_xor(t, 8);
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        acc[u][v][i] = t;
+      }
+    __builtin_amdgcn_sched_barrier(0);  // one tile row at a time: bounded temporaries
+  }
+  if (lane < 4) {
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+#pragma unroll
+      for (int v = 0; v < T; ++v)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[w][(u * T + v) * 4 + lane][i] = acc[u][v][i];
+  }
+  __syncthreads();
+  // the 4 waves in fixed order; entry (u, v, j, i) is dH[a, b0+4u+j, c0+4v+i]
+  for (int e = tid; e < T * T * 16; e += HTHREADS) {
+    const int i = e & 3, j = (e >> 2) & 3, uv = e >> 4, u = uv / T, v = uv - u * T;
+    const int b = b0 + 4 * u + j, c = c0 + 4 * v + i;
+    if (b < d.ky && c < d.kx && b < b0 + 4 * d.tb && c < c0 + 4 * d.tc) {
+      const float sum = ((red[0][uv * 4 + j][i] + red[1][uv * 4 + j][i]) + red[2][uv * 4 + j][i]) + red[3][uv * 4 + j][i];
+      part[(int64_t)split * d.kz * d.ky * d.kx + ((int64_t)a * d.ky + b) * d.kx + c] = sum;
+    }
+  }
+}
+
 }  // namespace
 
 bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype) {
+  if (dtype == NDC_F32) return true;  // matrix-core form: any PSF (blocks of 24 x 24)
   const DhGeom d = dh_geom(m3, p3);
-  const size_t es = dtype == NDC_F64 ? 8 : 4;
-  return d.ky * d.ncg <= 256 && dh_lds_bytes(d, es) <= 96 * 1024;
+  return d.ky * d.ncg <= 256 && dh_lds_bytes(d, 8) <= 96 * 1024;
 }
 
 size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype) {
+  if (dtype == NDC_F32) {
+    const DhmGeom d = dhm_geom(m3, p3);
+    return (size_t)d.nsplit * d.kz * d.ky * d.kx * sizeof(float);
+  }
   const DhGeom d = dh_geom(m3, p3);
-  const size_t es = dtype == NDC_F64 ? 8 : 4;
-  return (size_t)d.nsplit * d.kz * d.ky * d.kx * es;
+  return (size_t)d.nsplit * d.kz * d.ky * d.kx * sizeof(double);
 }
 
 hipError_t launch_dh(const int64_t m3[3], const int64_t p3[3], int dtype, const void *X, const void *G, void *dH,
                      void *ws, hipStream_t s) {
+  if (dtype == NDC_F32) {
+    const DhmGeom d = dhm_geom(m3, p3);
+    const int64_t blocks = (int64_t)d.kz * d.nbb * d.nbc * d.nsplit;
+    const dim3 grid((unsigned)blocks), block(HTHREADS);
+    switch (max(d.tb, d.tc)) {
+#define NDC_DHM(T)                                                                                            \
+  case T:                                                                                                      \
+    hipLaunchKernelGGL(dh_mfma_kernel<T>, grid, block, 0, s, (const float *)X, (const float *)G, (float *)ws, d); \
+    break;
+      NDC_DHM(1) NDC_DHM(2) NDC_DHM(3) NDC_DHM(4) NDC_DHM(5) NDC_DHM(6)
+#undef NDC_DHM
+      default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_splitk_reduce(dtype, ws, dH, (int64_t)d.kz * d.ky * d.kx, d.nsplit, s);
+  }
   const DhGeom d = dh_geom(m3, p3);
   const size_t es = dtype == NDC_F64 ? 8 : 4;
   const int threads = ((d.ky * d.ncg + 63) / 64) * 64;

@@ -93,8 +93,15 @@ def test_reduced_precision(nd, m, p, prec):
     assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[prec]
 
 
+# dH cases: one and several 128-column / 16-row tiles with ragged tails, PSF
+# rows or columns spanning several 24-wide blocks, 1x1x1 PSF, 1-D and 2-D
+DH_CASES = [((6, 9, 11), (1, 2, 3)), ((16, 40, 40), (3, 2, 4)), ((20, 33), (2, 5)),
+            ((4, 50, 300), (1, 13, 2)), ((3, 70, 140), (2, 3, 14)), ((2, 20, 130), (0, 0, 0)),
+            ((300,), (7,)), ((5, 37, 29), (2, 10, 10))]
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
-@pytest.mark.parametrize("m,p", [((6, 9, 11), (1, 2, 3)), ((16, 40, 40), (3, 2, 4)), ((20, 33), (2, 5))])
+@pytest.mark.parametrize("m,p", DH_CASES)
 def test_conv_dH(nd, m, p, dtype):
     say("case dH m=%s p=%s %s" % (m, p, dtype))
     rng = np.random.default_rng(5)
