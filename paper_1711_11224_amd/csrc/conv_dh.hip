@@ -135,27 +135,26 @@ size_t dh_lds_bytes(const DhGeom &d, size_t es) {
 //
 // Work-group (a, PSF block, split s): PSF plane a, one block of rows/columns
 // of it, X plane z and a range of G rows (the split).  G and X tiles of
-// 16 G rows x 128 columns (with the X halo of the block's rows) are staged in
-// LDS; wave w takes G rows 4w .. 4w+3 of each tile.  At the end the 16 x
+// 16 or 32 G rows x 128 columns (with the X halo of the block's rows) are
+// staged in LDS; wave w takes a quarter of the rows of each tile.  At the end the 16 x
 // blocks and the 4 waves are summed in fixed order and the split's partial
 // PSF block is written; the splits are added in double precision afterwards.
-constexpr int HQY = 16;              // G rows per staged tile
 constexpr int HQX = 128;             // X columns per staged tile
 constexpr int HMT = 6;               // max 4-wide tiles per block along b and c
 constexpr int HXS = HQX + 16;        // X tile row stride (= 16 mod 64: 4 rows x 16 lanes, no bank conflict)
-constexpr int HXR = HQY + 4 * HMT - 1;                  // X tile rows (39)
 constexpr int HGS = HQX + 4 * HMT + 4;                  // G tile row stride (>= 128 + 23 + 1)
-constexpr int HLDS = HXR * HXS + HQY * HGS;             // floats
 constexpr int HTHREADS = 256;
+__host__ __device__ constexpr int dh_tile_rows(int t) { return t >= 6 ? 32 : 16; }
 
 struct DhmGeom {
   int mz, my, mx, kz, ky, kx, gy, gx;
   int tb, tc, nbb, nbc;   // tiles per block along b / c, blocks along b / c
-  int nys, ysplit;        // G-row splits per X plane, G rows per split (multiple of HQY)
+  int nys, ysplit;        // G-row splits per X plane, G rows per split (multiple of the tile height)
   int nsplit;             // mz * nys
 };
 
 DhmGeom dhm_geom(const int64_t m3[3], const int64_t p3[3]) {
+  int HQY;
   DhmGeom d;
   d.mz = (int)m3[0];
   d.my = (int)m3[1];
@@ -170,6 +169,7 @@ DhmGeom dhm_geom(const int64_t m3[3], const int64_t p3[3]) {
   d.nbc = (ntc + HMT - 1) / HMT;
   d.tb = (ntb + d.nbb - 1) / d.nbb;
   d.tc = (ntc + d.nbc - 1) / d.nbc;
+  HQY = dh_tile_rows(d.tb > d.tc ? d.tb : d.tc);
   // split G rows only as far as needed to give the chip ~2048 work-groups
   const int64_t base = (int64_t)d.kz * d.nbb * d.nbc * d.mz;
   const int ytiles = (d.gy + HQY - 1) / HQY;
@@ -198,7 +198,9 @@ __device__ __forceinline__ void dh_sfor(F &&f) {
 template <int T>
 __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__restrict__ X, const float *__restrict__ G,
                                                               float *__restrict__ part, DhmGeom d) {
-  __shared__ __align__(16) float lds[HLDS];
+  constexpr int HQY = dh_tile_rows(T);             // G rows per staged tile (HQY / 4 per wave)
+  constexpr int HXR = HQY + 4 * T - 1;             // X tile rows
+  __shared__ __align__(16) float lds[HXR * HXS + HQY * HGS];
   __shared__ float red[4][4 * HMT * HMT][4];  // [wave][tile*4 + j][i]
   float *xt = lds;                 // HXR x HXS
   float *gt = lds + HXR * HXS;     // HQY x HGS
@@ -244,8 +246,8 @@ __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__res
       __syncthreads();
       const int nch = min(HQX, d.mx - xt0 + 15) / 16;  // 16-wide chunks with any X column
 #pragma unroll 1
-      for (int r = 0; r < 4; ++r) {
-        const int row = 4 * w + r;  // G row inside the tile
+      for (int r = 0; r < HQY / 4; ++r) {
+        const int row = (HQY / 4) * w + r;  // G row inside the tile
         if (yt + row >= y_hi) break;
 #pragma unroll 1
         for (int ch = 0; ch < nch; ++ch) {
