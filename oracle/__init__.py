@@ -272,7 +272,38 @@ def initial_delta(h, lam=0.0):
     return 1.0 / (float(np.sum(np.abs(_d(h)))) ** 2 + lam)
 
 
-def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None):
+STEP_RULES = ("fixed", "cauchy", "bb")
+
+
+def first_trial(rule, g, h, lam, d0, s_prev=None, g_prev=None):
+    """First trial step of one iteration.  The paper's rule only demands that
+    the accepted delta_k decreases f; the first trial is free:
+
+      fixed:  delta_0 = 1/(||h||_1^2 + lam) every iteration;
+      cauchy: the exact line minimiser along -g of the unprojected objective,
+              <g,g> / (||A g||^2 + lam ||g||^2);
+      bb:     Barzilai-Borwein, <s,s> / <s,y> with s = X^k - X^{k-1} and
+              y = g^k - g^{k-1} (delta_0 on the first iteration).
+
+    A non-positive or non-finite quotient falls back to delta_0."""
+    if rule == "fixed":
+        return d0
+    if rule == "cauchy":
+        ag = conv_full(g, h)
+        num = float(np.sum(g * g))
+        den = float(np.sum(ag * ag)) + lam * num
+    elif rule == "bb":
+        if s_prev is None:
+            return d0
+        num = float(np.sum(s_prev * s_prev))
+        den = float(np.sum(s_prev * (g - g_prev)))
+    else:
+        raise ValueError("unknown step rule %r" % (rule,))
+    q = num / den if den > 0 else np.inf
+    return q if np.isfinite(q) and q > 0 else d0
+
+
+def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None, rule="fixed"):
     """Non-negative projected gradient of the section "Application to
     2-dimensional deconvolution", applied to any n:
 
@@ -286,7 +317,8 @@ def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None):
     and halve on failure, at most jmax trials; equality counts as failure.
     If no trial decreases f, or f becomes non-finite, the loop stops early.
     With deltas given (one per step) the steps are replayed with those values
-    and no test.
+    and no test.  `rule` picks the first trial of each iteration (see
+    first_trial); the halving that follows is the same for every rule.
 
     Returns (X, stats, iters_done, status): stats rows (f_k, delta_k,
     rejections_k, ||X^{k+1}-X^k||_2), row 0 holding f(X^0); status 0 for a
@@ -297,6 +329,7 @@ def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None):
     stats = [(f_k, np.nan, 0.0, np.nan)]
     d0 = initial_delta(h, lam)
     done, status = 0, 0
+    s_prev = g_prev = None
     if not np.isfinite(f_k):
         return x, np.array(stats), 0, 2
     for k in range(iters):
@@ -312,7 +345,7 @@ def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None):
             stats.append((f_t, d, 0.0, float(np.linalg.norm(xt - x))))
             x, f_k, done = xt, f_t, done + 1
             continue
-        d, rej, accepted = d0, 0, False
+        d, rej, accepted = first_trial(rule, g, h, lam, d0, s_prev, g_prev), 0, False
         for _ in range(jmax):
             xt = np.maximum(x - d * g, 0.0)
             f_t = objective(xt, y, h, lam)
@@ -328,5 +361,6 @@ def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None):
             status = status or 1
             break
         stats.append((f_t, d, float(rej), float(np.linalg.norm(xt - x))))
+        s_prev, g_prev = xt - x, g
         x, f_k, done = xt, f_t, done + 1
     return x, np.array(stats), done, status

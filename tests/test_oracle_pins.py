@@ -316,3 +316,83 @@ def test_deconv_replay_matches_search():
     xa, sa, da, _ = oracle.deconv(y, h, x0, 10)
     xb, sb, db, _ = oracle.deconv(y, h, x0, 10, deltas=sa[1:, 1])
     np.testing.assert_array_equal(xa, xb)
+
+
+# ---- step-size rules (first trial of an iteration; halving as before) ----
+
+def _grad(x, y, h, lam):
+    return oracle.conv_adjoint(oracle.conv_full(x, h) - y, h) + lam * x
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_cauchy_trial_minimises_along_the_gradient(lam):
+    """Away from the bound the Cauchy trial is the exact minimiser of
+    f(X - t g) over t: the directional derivative vanishes there and nearby
+    t give larger f."""
+    rng = np.random.default_rng(21)
+    h = rng.random((3, 5, 3))
+    y = oracle.conv_full(50.0 + rng.random((4, 9, 7)), h)
+    x = 50.0 + rng.random((4, 9, 7))          # far above 0: no clipping
+    g = _grad(x, y, h, lam)
+    d = oracle.first_trial("cauchy", g, h, lam, oracle.initial_delta(h, lam))
+    xt = x - d * g
+    assert xt.min() > 0
+    slope = float(np.sum(g * _grad(xt, y, h, lam)))
+    assert abs(slope) <= 1e-10 * float(np.sum(g * g))
+    f = oracle.objective(xt, y, h, lam)
+    for t in (0.5, 0.9, 1.1, 2.0):
+        assert oracle.objective(x - t * d * g, y, h, lam) > f
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_bb_trial_is_the_secant_quotient(lam):
+    """f is quadratic, so g(X1) - g(X0) = (A^T A + lam) (X1 - X0) for any two
+    points: the BB quotient from gradient differences equals
+    <s,s> / (||A s||^2 + lam ||s||^2) from a direct forward of s."""
+    rng = np.random.default_rng(22)
+    h = rng.random((1, 3, 5))
+    y = oracle.conv_full(rng.random((3, 6, 8)), h)
+    x0, x1 = rng.random((3, 6, 8)), rng.random((3, 6, 8))
+    g0, g1 = _grad(x0, y, h, lam), _grad(x1, y, h, lam)
+    s = x1 - x0
+    d = oracle.first_trial("bb", g1, h, lam, oracle.initial_delta(h, lam), s, g0)
+    a_s = oracle.conv_full(s, h)
+    ref = float(np.sum(s * s)) / (float(np.sum(a_s * a_s)) + lam * float(np.sum(s * s)))
+    assert abs(d - ref) <= 1e-12 * ref
+
+
+def test_bb_second_trial_is_first_cauchy_step():
+    """With an unclipped first step s = -delta0 g0, the BB quotient of the
+    second iteration reduces to the Cauchy trial at X^0."""
+    rng = np.random.default_rng(23)
+    h = rng.random((3, 3, 3))
+    y = oracle.conv_full(50.0 + rng.random((4, 8, 8)), h)
+    x0 = 50.0 + rng.random((4, 8, 8))
+    _, sb, done, _ = oracle.deconv(y, h, x0, 2, rule="bb")
+    _, sc, _, _ = oracle.deconv(y, h, x0, 1, rule="cauchy")
+    assert done == 2 and sb[1, 2] == 0 and sb[2, 2] == 0
+    assert sb[1, 1] == oracle.initial_delta(h)
+    assert abs(sb[2, 1] - sc[1, 1]) <= 1e-12 * sc[1, 1]
+
+
+@pytest.mark.parametrize("rule", ["cauchy", "bb"])
+def test_step_rules_decrease_and_stay_nonnegative(rule):
+    rng = np.random.default_rng(24)
+    h = rng.random((3, 5, 5))
+    y = oracle.conv_full(rng.random((4, 12, 12)), h) + 0.01
+    x, st, done, status = oracle.deconv(y, h, np.full((4, 12, 12), 0.5), 12, rule=rule)
+    assert done == 12 and status == 0
+    assert np.all(np.diff(st[:, 0]) < 0)
+    assert x.min() >= 0
+    # faster than the fixed first trial on this problem
+    _, sf, _, _ = oracle.deconv(y, h, np.full((4, 12, 12), 0.5), 12)
+    assert st[-1, 0] < sf[-1, 0]
+
+
+def test_bb_falls_back_without_curvature():
+    h = np.ones((3, 3))
+    g = np.ones((4, 4))
+    d0 = oracle.initial_delta(h)
+    assert oracle.first_trial("bb", g, h, 0.0, d0, np.zeros((4, 4)), g) == d0   # <s,y> = 0
+    assert oracle.first_trial("bb", g, h, 0.0, d0, None, None) == d0            # first iteration
+    assert oracle.first_trial("cauchy", np.zeros((4, 4)), h, 0.0, d0) == d0     # g = 0
