@@ -134,10 +134,18 @@ def deconv_workspace_bytes(shape, psf_shape, dtype=torch.float32, precision="nat
     return int(lib.deconv_workspace_bytes(len(shape), i64_array(shape), i64_array(p), dt, _prec(precision)))
 
 
-def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=None, info=None, stream=None):
+STEP_RULES = {"fixed": 0, "cauchy": 1, "bb": 2}
+
+
+def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=None, info=None, stream=None,
+                   rule="fixed"):
     """Run `iters` accepted projected-gradient steps in place on X (Steps 1-3,
-    delta accepted by f(X^{k+1}) < f(X^k)).  Returns (X, stats, info) with
-    stats (iters+1, 4) float64 and info (2,) int32 on the device."""
+    delta accepted by f(X^{k+1}) < f(X^k)).  `rule` picks the first trial of
+    each iteration: "fixed" (delta_0), "cauchy" or "bb" (see ndconv.h).
+    Returns (X, stats, info) with stats (iters+1, 4) float64 and info (2,)
+    int32 on the device."""
+    if rule not in STEP_RULES:
+        raise ValueError("rule must be one of %s" % sorted(STEP_RULES))
     for t, nm in ((Y, "Y"), (H, "H"), (X, "X")):
         _dev(t, nm)
     if not (Y.dtype == H.dtype == X.dtype):
@@ -153,9 +161,14 @@ def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=N
         stats = torch.full((iters + 1, 4), float("nan"), dtype=torch.float64, device=X.device)
     if info is None:
         info = torch.zeros(2, dtype=torch.int32, device=X.device)
-    check(lib.deconv_iterate(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam), dt, pr,
-                             ws.data_ptr(), ws.numel() * ws.element_size(), stats.data_ptr(), info.data_ptr(),
-                             _stream(stream)), "deconv_iterate")
+    if rule == "fixed":
+        check(lib.deconv_iterate(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam), dt, pr,
+                                 ws.data_ptr(), ws.numel() * ws.element_size(), stats.data_ptr(), info.data_ptr(),
+                                 _stream(stream)), "deconv_iterate")
+    else:
+        check(lib.deconv_iterate_rule(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam),
+                                      dt, pr, STEP_RULES[rule], ws.data_ptr(), ws.numel() * ws.element_size(),
+                                      stats.data_ptr(), info.data_ptr(), _stream(stream)), "deconv_iterate_rule")
     return X, stats, info
 
 
@@ -168,7 +181,7 @@ def conv_adjoint(r, h, precision="native"):
     return conv_adjoint_nd(r.contiguous(), h.contiguous(), precision=precision)
 
 
-def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native"):
+def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed"):
     """Projected-gradient deconvolution; x0 defaults to the flux-matching flat
     start max(sum Y, 0)/(N sum H).  Returns (x, stats, info)."""
     y, h = y.contiguous(), h.contiguous()
@@ -183,4 +196,4 @@ def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native"):
         x.fill_(float(val))
     else:
         x = x0.clone().contiguous()
-    return deconv_iterate(y, h, x, iters, lam=lam, precision=precision)
+    return deconv_iterate(y, h, x, iters, lam=lam, precision=precision, rule=rule)

@@ -13,7 +13,7 @@ namespace ndc {
 
 size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision);
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
-               double lambda, int dtype, int precision, void *ws, double *stats, int *info, hipStream_t s);
+               double lambda, int dtype, int precision, void *ws, double *stats, int *info, int rule, hipStream_t s);
 bool mfma_supported(const Geom &g, int dtype, int precision);
 bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype);
 size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype);
@@ -304,9 +304,10 @@ size_t deconv_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dty
   return deconv_ws_bytes(E.m3, E.p3, dtype, precision);
 }
 
-int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
-                   double lambda, int dtype, int precision, void *ws, size_t ws_bytes, double *stats, int *info,
-                   void *stream) {
+static int deconv_checked(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
+                          int iters, double lambda, int dtype, int precision, int rule, void *ws, size_t ws_bytes,
+                          double *stats, int *info, void *stream) {
+  if (rule != NDC_STEP_FIXED && rule != NDC_STEP_CAUCHY && rule != NDC_STEP_BB) return NDC_EINVAL;
   Extents E;
   int rc = prepare(n, m, p, dtype, precision, E);
   if (rc) return rc;
@@ -327,7 +328,22 @@ int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, con
   }
   if (!device_ptr(Y) || !device_ptr(H) || !device_ptr(X) || !device_ptr(ws)) return NDC_EINVAL;
   if ((stats && !device_ptr(stats)) || (info && !device_ptr(info))) return NDC_EINVAL;
-  return deconv_run(E.m3, E.p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, (hipStream_t)stream);
+  return deconv_run(E.m3, E.p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, rule,
+                    (hipStream_t)stream);
+}
+
+int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
+                   double lambda, int dtype, int precision, void *ws, size_t ws_bytes, double *stats, int *info,
+                   void *stream) {
+  return deconv_checked(n, m, p, Y, H, X, iters, lambda, dtype, precision, NDC_STEP_FIXED, ws, ws_bytes, stats,
+                        info, stream);
+}
+
+int deconv_iterate_rule(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
+                        double lambda, int dtype, int precision, int rule, void *ws, size_t ws_bytes, double *stats,
+                        int *info, void *stream) {
+  return deconv_checked(n, m, p, Y, H, X, iters, lambda, dtype, precision, rule, ws, ws_bytes, stats, info,
+                        stream);
 }
 
 }  // extern "C"

@@ -10,6 +10,13 @@
 //   5. commit (only right after an acceptance): X <- X_t, R <- R_t
 // Rejections happen only at rounding-level stationarity with the adopted
 // delta_0, so the host normally launches `iters` steps and waits once.
+//
+// With a Cauchy or Barzilai-Borwein first trial the gradient comes first and
+// the trial is computed from it on the device:
+//   1. transpose of R with the GRAD epilogue     (phase NEW):   G, <g,g>, <s,dg>
+//   1b. forward of G with the NORM epilogue      (NEW, Cauchy): ||A g||^2
+//   1c. step (one work-group): delta from the rule, phase -> RETRY
+// and steps 2-5 follow as for a halved retry.
 #include <math.h>
 
 #include "ndc_device.h"
@@ -39,7 +46,7 @@ __device__ double wg_sum(const double *part, int64_t cnt, int comp, double (*red
 
 template <typename T>
 __global__ __launch_bounds__(ET) void init_kernel(const T *__restrict__ H, int64_t nh, double lambda, int iters,
-                                                  int jmax, DState *st) {
+                                                  int jmax, int rule, DState *st) {
   __shared__ double red[ET / 64][2];
   double s = 0.0, dummy = 0.0;
   for (int64_t i = threadIdx.x; i < nh; i += ET) s += fabs((double)H[i]);
@@ -56,7 +63,40 @@ __global__ __launch_bounds__(ET) void init_kernel(const T *__restrict__ H, int64
     st->iters = iters;
     st->jmax = jmax;
     st->accepted = 0;
+    st->rule = rule;
+    st->ss = 0.0;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(ET) void zero_kernel(T *__restrict__ a, T *__restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < n; i += (int64_t)gridDim.x * ET) {
+    a[i] = (T)0;
+    b[i] = (T)0;
+  }
+}
+
+// First trial of a Cauchy / BB iteration from the gradient partials (GRAD
+// epilogue: <g,g>, <s, g - g_old>) and, for Cauchy, ||A g||^2 (NORM epilogue).
+__global__ __launch_bounds__(ET) void step_kernel(DState *st, const double *part_grad, int64_t ng,
+                                                  const double *part_ag, int64_t na) {
+  if (st->phase != PH_NEW) return;
+  __shared__ double red[ET / 64][2];
+  const double gg = wg_sum(part_grad, ng, 0, red);
+  const double sy = wg_sum(part_grad, ng, 1, red);
+  const double ag = st->rule == NDC_STEP_CAUCHY ? wg_sum(part_ag, na, 0, red) : 0.0;
+  if (threadIdx.x != 0) return;
+  double num = 0.0, den = 0.0;
+  if (st->rule == NDC_STEP_CAUCHY) {
+    num = gg;
+    den = ag + st->lambda * gg;
+  } else if (st->k > 0) {  // BB; delta_0 on the first iteration of a call
+    num = st->ss;
+    den = sy;
+  }
+  const double q = den > 0.0 ? num / den : 0.0;
+  st->delta = (isfinite(q) && q > 0.0) ? q : st->delta0;
+  st->phase = PH_RETRY;
 }
 
 template <typename T>
@@ -153,6 +193,7 @@ __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *pa
     }
     st->k = k;
     st->f_cur = ft;
+    st->ss = dx2;
     st->rej = 0;
     st->delta = st->delta0;
     st->accepted = 1;
@@ -177,17 +218,20 @@ __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *pa
 template <typename T>
 __global__ __launch_bounds__(ET) void commit_kernel(const DState *st, T *__restrict__ X, const T *__restrict__ Xt,
                                                     int64_t n, T *__restrict__ R, const T *__restrict__ Rt,
-                                                    int64_t ny) {
+                                                    int64_t ny, T *__restrict__ S) {
   if (!st->accepted) return;
   const int64_t m = n > ny ? n : ny;
   for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < m; i += (int64_t)gridDim.x * ET) {
-    if (i < n) X[i] = Xt[i];
+    if (i < n) {
+      if (S) S[i] = Xt[i] - X[i];  // BB: the accepted step
+      X[i] = Xt[i];
+    }
     if (i < ny) R[i] = Rt[i];
   }
 }
 
 struct WsLayout {
-  size_t state, part_fwd, part_upd, xt, g, r, rt, total;
+  size_t state, part_fwd, part_upd, xt, g, r, rt, sbuf, total;
 };
 
 WsLayout layout(int64_t N, int64_t NY, size_t esz, int64_t nf, int64_t nu) {
@@ -207,6 +251,8 @@ WsLayout layout(int64_t N, int64_t NY, size_t esz, int64_t nf, int64_t nu) {
   o += align256((size_t)NY * esz);
   L.rt = o;
   o += align256((size_t)NY * esz);
+  L.sbuf = o;  // accepted step X^k - X^{k-1} (Barzilai-Borwein rule)
+  o += align256((size_t)N * esz);
   L.total = o;
   return L;
 }
@@ -233,7 +279,7 @@ Sizes sizes_for(const int64_t m3[3], const int64_t p3[3], int dtype, int precisi
 
 template <typename T>
 int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *Xv, int iters,
-             double lambda, int dtype, int precision, void *ws, double *stats, int *info, hipStream_t s) {
+             double lambda, int dtype, int precision, void *ws, double *stats, int *info, int rule, hipStream_t s) {
   const Sizes S = sizes_for(m3, p3, dtype, precision);
   const int64_t nu = S.pa.nblocks > S.n_ew ? S.pa.nblocks : S.n_ew;
   const WsLayout L = layout(S.N, S.NY, sizeof(T), S.pf.nblocks, nu);
@@ -242,8 +288,10 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   double *part_fwd = (double *)(w + L.part_fwd);
   double *part_upd = (double *)(w + L.part_upd);
   T *X = (T *)Xv, *Xt = (T *)(w + L.xt), *G = (T *)(w + L.g), *R = (T *)(w + L.r), *Rt = (T *)(w + L.rt);
+  T *Sb = rule == NDC_STEP_BB ? (T *)(w + L.sbuf) : nullptr;
 
-  hipLaunchKernelGGL(init_kernel<T>, dim3(1), dim3(ET), 0, s, (const T *)H, S.NH, lambda, iters, 30, st);
+  hipLaunchKernelGGL(init_kernel<T>, dim3(1), dim3(ET), 0, s, (const T *)H, S.NH, lambda, iters, 30, rule, st);
+  if (Sb) hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, Sb, G, S.N);
   hipLaunchKernelGGL(sumsq_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, S.N, part_upd);
   Epi ef{};
   ef.mode = EPI_RESID;
@@ -264,6 +312,19 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   ea.part = part_upd;
   ea.phase = &st->phase;
   ea.phase_mask = 1 << PH_NEW;
+  Epi eg{};  // Cauchy / BB: gradient first
+  eg.mode = EPI_GRAD;
+  eg.X = X;
+  eg.lambda = lambda;
+  eg.part = part_upd;
+  eg.phase = &st->phase;
+  eg.phase_mask = 1 << PH_NEW;
+  eg.S = Sb;
+  Epi en{};  // Cauchy: ||A g||^2
+  en.mode = EPI_NORM;
+  en.part = part_fwd;
+  en.phase = &st->phase;
+  en.phase_mask = 1 << PH_NEW;
   Epi et{};
   et.mode = EPI_RESID;
   et.Y = Y;
@@ -275,14 +336,23 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   int remaining = iters;
   while (remaining > 0) {
     for (int step = 0; step < remaining; ++step) {
-      if (launch_conv(S.pa, S.ga, dtype, precision, R, H, Xt, ea, s) != hipSuccess) return NDC_EDEVICE;
+      if (rule == NDC_STEP_FIXED) {
+        if (launch_conv(S.pa, S.ga, dtype, precision, R, H, Xt, ea, s) != hipSuccess) return NDC_EDEVICE;
+      } else {
+        if (launch_conv(S.pa, S.ga, dtype, precision, R, H, G, eg, s) != hipSuccess) return NDC_EDEVICE;
+        // (NORM stores nothing; R_t is passed as a valid, unused output)
+        if (rule == NDC_STEP_CAUCHY && launch_conv(S.pf, S.gf, dtype, precision, G, H, Rt, en, s) != hipSuccess)
+          return NDC_EDEVICE;
+        hipLaunchKernelGGL(step_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_upd, S.pa.nblocks,
+                           (const double *)part_fwd, S.pf.nblocks);
+      }
       hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, (const T *)G, Xt,
                          S.N, (const DState *)st, part_upd);
       if (launch_conv(S.pf, S.gf, dtype, precision, Xt, H, Rt, et, s) != hipSuccess) return NDC_EDEVICE;
       hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_fwd, S.pf.nblocks,
                          (const double *)part_upd, S.pa.nblocks, S.n_ew, stats, info);
       hipLaunchKernelGGL(commit_kernel<T>, dim3((unsigned)ncommit), dim3(ET), 0, s, (const DState *)st, X,
-                         (const T *)Xt, S.N, R, (const T *)Rt, S.NY);
+                         (const T *)Xt, S.N, R, (const T *)Rt, S.NY, Sb);
       if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
     }
     DState h;
@@ -304,9 +374,10 @@ size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int 
 }
 
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
-               double lambda, int dtype, int precision, void *ws, double *stats, int *info, hipStream_t s) {
-  if (dtype == NDC_F64) return deconv_t<double>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, s);
-  return deconv_t<float>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, s);
+               double lambda, int dtype, int precision, void *ws, double *stats, int *info, int rule, hipStream_t s) {
+  if (dtype == NDC_F64)
+    return deconv_t<double>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, rule, s);
+  return deconv_t<float>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, rule, s);
 }
 
 }  // namespace ndc

@@ -134,3 +134,10 @@ def test_batch_plan_argument_checks():
     assert lib.ndc_batch_plan_create(1, I([4, 4, 4]), I([1, 1, 1]), F32, 0, None, None) == nd.NDC_EINVAL
     assert lib.ndc_batch_workspace_bytes(None) == 0
     lib.ndc_batch_plan_destroy(None)  # no-op
+
+
+def test_deconv_rule_rejects_unknown_rule():
+    """An unknown step rule is refused before any pointer is looked at."""
+    rc = lib.deconv_iterate_rule(3, I([4, 4, 4]), I([1, 1, 1]), None, None, None, 1, 0.0, F32, 0, 7, None, 0,
+                                 None, None, None)
+    assert rc == -1

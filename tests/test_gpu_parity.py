@@ -143,18 +143,19 @@ def test_errors_on_device(nd):
 
 
 # ---------------------------------------------------------------- deconvolution
-def _check_deconv(nd, y, h, x0, iters, lam, npdt, tol_x, tol_f, prec="native"):
-    xg, st, info = nd.deconv_iterate(gpu(y, npdt), gpu(h, npdt), gpu(x0, npdt), iters, lam=lam, precision=prec)
+def _check_deconv(nd, y, h, x0, iters, lam, npdt, tol_x, tol_f, prec="native", rule="fixed", tol_d=1e-14):
+    xg, st, info = nd.deconv_iterate(gpu(y, npdt), gpu(h, npdt), gpu(x0, npdt), iters, lam=lam, precision=prec,
+                                     rule=rule)
     torch.cuda.synchronize()
     xo, so, done, status = oracle.deconv(y.astype(np.float64), h.astype(np.float64), x0.astype(np.float64),
-                                         iters, lam=lam)
+                                         iters, lam=lam, rule=rule)
     inf = info.cpu().numpy()
     stg = st.cpu().numpy()
     assert int(inf[0]) == done and int(inf[1]) == status
     # the accept/reject decisions must agree exactly; delta_0 = 1/||H||_1^2 is a
     # double sum taken in a different order on each side, so allow rounding
     np.testing.assert_array_equal(stg[1:done + 1, 2], so[1:done + 1, 2])
-    np.testing.assert_allclose(stg[1:done + 1, 1], so[1:done + 1, 1], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(stg[1:done + 1, 1], so[1:done + 1, 1], rtol=tol_d, atol=0)
     assert rel_l2(xg.cpu().numpy(), xo) <= tol_x
     f_g, f_o = stg[:done + 1, 0], so[:done + 1, 0]
     assert np.all(np.abs(f_g - f_o) <= tol_f * np.abs(f_o))
@@ -185,6 +186,59 @@ def test_deconv_fp32_small(nd, lam):
     y = y.astype(np.float32)
     x0 = np.full(m, 0.4, dtype=np.float32)
     _check_deconv(nd, y, h, x0, 20, lam, np.float32, 1e-5, 1e-5)
+
+
+@pytest.mark.parametrize("rule", ["cauchy", "bb"])
+def test_deconv_step_rules_fp64(nd, rule):
+    """Cauchy / Barzilai-Borwein first trials against the oracle, 2-D FP64
+    (64x64 X, 9x9 PSF, Poisson noise): same decisions, deltas to 1e-9."""
+    cfg = synth.CONFIGS["c1_2d_f64"]
+    say("case deconv rule %s fp64" % rule)
+    x_true = synth.make_objects(cfg)
+    h = synth.psf_for(cfg)
+    y = synth.add_noise(oracle.conv_full(x_true, h), cfg)
+    x0 = synth.flat_start(y, h, cfg.shape)
+    _check_deconv(nd, y, h, x0, 30, 0.0, np.float64, 1e-8, 1e-11, rule=rule, tol_d=1e-9)
+
+
+def _rule_problem_fp32():
+    rng = np.random.default_rng(31)
+    m, p = (6, 24, 70), (2, 3, 5)
+    h = synth.gaussian_psf([2 * q + 1 for q in p], (1.0, 1.5, 2.0)).astype(np.float32)
+    y = (oracle.conv_full(rng.random(m), h) + 0.05 * rng.standard_normal([a + 2 * b for a, b in zip(m, p)]))
+    return y.astype(np.float32), h, np.full(m, 0.4, dtype=np.float32)
+
+
+@pytest.mark.parametrize("rule", ["cauchy", "bb"])
+@pytest.mark.parametrize("lam", [0.0, 0.3])
+def test_deconv_step_rules_fp32(nd, rule, lam):
+    """FP32 3-D with the first trial from FP32 gradients (FP64 sums), element
+    by element against the oracle for 8 iterations.  Later on the BB quotient
+    <s,s>/<s,dg> is formed from ever smaller gradient differences and follows
+    the FP32 rounding of the gradients (at iteration 10 here the two sides
+    need different numbers of halvings), so longer runs are checked by the
+    properties below."""
+    say("case deconv rule %s fp32 lam=%g" % (rule, lam))
+    y, h, x0 = _rule_problem_fp32()
+    _check_deconv(nd, y, h, x0, 8, lam, np.float32, 1e-4, 1e-5, rule=rule, tol_d=1e-4)
+
+
+@pytest.mark.parametrize("rule", ["cauchy", "bb"])
+def test_deconv_step_rules_fp32_long(nd, rule):
+    """40 FP32 iterations: strict decrease, X >= 0, and a lower objective
+    than the fixed first trial reaches in the same number of iterations."""
+    say("case deconv rule %s fp32 long" % rule)
+    y, h, x0 = _rule_problem_fp32()
+    res = {}
+    for r in ("fixed", rule):
+        xg, st, info = nd.deconv_iterate(gpu(y, np.float32), gpu(h, np.float32), gpu(x0, np.float32), 40, rule=r)
+        torch.cuda.synchronize()
+        inf, stg = info.cpu().tolist(), st.cpu().numpy()
+        assert inf == [40, 0]
+        assert np.all(np.diff(stg[:, 0]) < 0)
+        assert xg.min().item() >= 0
+        res[r] = stg[-1, 0]
+    assert res[rule] < res["fixed"]
 
 
 def test_deconv_stops_without_descent(nd):
