@@ -197,6 +197,34 @@ def time_plan_pair(plan, torch, xs, hs, reps=3):
     return e0.elapsed_time(e1) / reps
 
 
+def bench_step_rules(nd, torch, y, h, x0, ws, steps=10, fixed_max=60):
+    """First-trial rules of the projected-gradient iteration on the metric
+    workload: time per step, objective after `steps` steps, and how many steps
+    the fixed first trial needs to reach that objective."""
+    def run(rule, n):
+        x = x0.clone()
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        _, st, info = nd.deconv_iterate(y, h, x, n, ws=ws, rule=rule)
+        e1.record(s)
+        torch.cuda.synchronize()
+        done = int(info.cpu()[0])
+        return e0.elapsed_time(e1), st.cpu().numpy()[: done + 1, 0], done
+    ms_f, f_fixed, done_f = run("fixed", fixed_max)
+    out = {"steps": steps, "fixed": {"ms_per_step": round(ms_f / max(done_f, 1), 3),
+                                     "f_after_steps": float(f_fixed[min(steps, done_f)])}}
+    for rule in ("cauchy", "bb"):
+        ms, f, done = run(rule, steps)
+        target = f[-1]
+        reach = [k for k in range(len(f_fixed)) if f_fixed[k] <= target]
+        out[rule] = {"ms_per_step": round(ms / max(done, 1), 3), "f_after_steps": float(target),
+                     "steps_done": done,
+                     "fixed_steps_to_match": reach[0] if reach else ">%d" % fixed_max}
+    return out
+
+
 def bench_small_psf(nd, torch, reps=5):
     """Small-PSF sweep on the metric volume (128x512x512), Gaussian PSFs 3^3,
     5^3, 7^3: HBM-bound operators, reported as algorithmic GB/s (4 (N + N_Y)
@@ -354,6 +382,8 @@ def main():
         "precisions": precisions,
     }
     if not args.no_extra:
+        out["step_rules"] = bench_step_rules(nd, torch, y, h, x0, ws)
+        log("step rules:", out["step_rules"])
         out["small_psf"] = bench_small_psf(nd, torch)
         log("small psf:", out["small_psf"])
         out["differentiable"] = bench_differentiable(nd, torch)
