@@ -225,6 +225,43 @@ def bench_step_rules(nd, torch, y, h, x0, ws, steps=10, fixed_max=60):
     return out
 
 
+def bench_paper_2d(nd, torch, iters=100):
+    """The paper's two 2-D experiment shapes on synthetic stand-ins (a 512x512
+    crossing-lines phantom with a 9x9 PSF, noise std 5; a 225x225 8-bit image
+    with a 5x5 PSF, noise std 20 and 5): `iters` iterations from the blurred
+    start max(crop(Y), 0) with each first-trial rule; time per iteration and
+    SNR = 10 log10(||X||^2/||X_est - X||^2) before and after."""
+    import synth
+    out = {}
+    for name, w in synth.PAPER_2D.items():
+        x = w["object"]()
+        h = synth.gaussian_psf(w["psf"], w["sigma"])
+        b = nd.conv_full(torch.from_numpy(x.astype(np.float32)).cuda(),
+                         torch.from_numpy(h.astype(np.float32)).cuda()).cpu().numpy().astype(np.float64)
+        p = [(e - 1) // 2 for e in w["psf"]]
+        for std in w["noise"]:
+            y = synth.gaussian_noise(b, std, seed=11)
+            x0 = np.maximum(y[p[0]:p[0] + x.shape[0], p[1]:p[1] + x.shape[1]], 0.0)
+            yg = torch.from_numpy(y.astype(np.float32)).cuda()
+            hg = torch.from_numpy(h.astype(np.float32)).cuda()
+            snr = lambda e: round(float(10 * np.log10(np.sum(x * x) / np.sum((np.asarray(e, np.float64) - x) ** 2))), 3)
+            rec = {"shape": list(x.shape), "psf": list(w["psf"]), "noise_std": std, "snr_blurred_db": snr(x0)}
+            for rule in ("fixed", "bb"):
+                xg = torch.from_numpy(x0.astype(np.float32)).cuda()
+                nd.deconv_iterate(yg, hg, xg.clone(), 2, rule=rule)  # warm-up
+                torch.cuda.synchronize()
+                s = torch.cuda.current_stream()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                _, st, info = nd.deconv_iterate(yg, hg, xg, iters, rule=rule)
+                e1.record(s)
+                torch.cuda.synchronize()
+                rec[rule] = {"ms_per_iter": round(e0.elapsed_time(e1) / iters, 4),
+                             "snr_db": snr(xg.cpu().numpy()), "iters_done": int(info.cpu()[0])}
+            out["%s_std%g" % (name, std)] = rec
+    return out
+
+
 def bench_small_psf(nd, torch, reps=5):
     """Small-PSF sweep on the metric volume (128x512x512), Gaussian PSFs 3^3,
     5^3, 7^3: HBM-bound operators, reported as algorithmic GB/s (4 (N + N_Y)
@@ -384,6 +421,8 @@ def main():
     if not args.no_extra:
         out["step_rules"] = bench_step_rules(nd, torch, y, h, x0, ws)
         log("step rules:", out["step_rules"])
+        out["paper_2d"] = bench_paper_2d(nd, torch)
+        log("paper 2-D shapes:", out["paper_2d"])
         out["small_psf"] = bench_small_psf(nd, torch)
         log("small psf:", out["small_psf"])
         out["differentiable"] = bench_differentiable(nd, torch)

@@ -11,8 +11,10 @@ Shapes are (z, y, x), C order, x contiguous.  The paper's own test images are
 not used: these inputs stand in for them with the shapes, value ranges and
 structure described in the design doc.
 """
-from .volumes import (CONFIGS, SWEEP_PSFS, VolumeConfig, add_noise, batched_configs,
-                      flat_start, gaussian_factors, gaussian_psf, make_objects, psf_for)
+from .volumes import (CONFIGS, PAPER_2D, SWEEP_PSFS, VolumeConfig, add_noise, batched_configs, crossing_lines,
+                      flat_start, gaussian_factors, gaussian_noise, gaussian_psf, make_objects, piecewise_image,
+                      psf_for)
 
-__all__ = ["CONFIGS", "SWEEP_PSFS", "VolumeConfig", "add_noise", "batched_configs", "flat_start",
-           "gaussian_factors", "gaussian_psf", "make_objects", "psf_for"]
+__all__ = ["CONFIGS", "PAPER_2D", "SWEEP_PSFS", "VolumeConfig", "add_noise", "batched_configs", "crossing_lines",
+           "flat_start", "gaussian_factors", "gaussian_noise", "gaussian_psf", "make_objects", "piecewise_image",
+           "psf_for"]

@@ -165,3 +165,68 @@ def batched_configs(count: int = 64, seed: int = 3) -> List[VolumeConfig]:
                                 n_points=max(1, int(500 * frac)), n_filaments=max(1, int(30 * frac)),
                                 iters=50))
     return out
+
+
+# ---- 2-D stand-ins for the paper's two experiments (its images are not
+# available): a 512x512 phantom of nine crossing lines, and a 225x225 8-bit
+# piecewise-smooth image blurred by a 5x5 PSF; both get additive Gaussian
+# white noise of a stated standard deviation.
+
+def crossing_lines(shape: Tuple[int, int] = (512, 512), n: int = 9, width: float = 3.0, amp: float = 255.0,
+                   seed: int = 7) -> np.ndarray:
+    """n straight lines across the image at distinct angles, each through a
+    point of the central half, `width` pixels wide with a one-pixel linear
+    edge, value amp on a zero background (max at crossings)."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.arange(shape[0], dtype=np.float64), np.arange(shape[1], dtype=np.float64),
+                         indexing="ij")
+    img = np.zeros(shape, dtype=np.float64)
+    angles = np.pi * (np.arange(n) + rng.uniform(0.1, 0.9, size=n)) / n
+    for a in angles:
+        cy, cx = rng.uniform(0.25, 0.75) * (shape[0] - 1), rng.uniform(0.25, 0.75) * (shape[1] - 1)
+        d = np.abs(-(yy - cy) * np.cos(a) + (xx - cx) * np.sin(a))   # distance to the line
+        np.maximum(img, amp * np.clip(width / 2 + 0.5 - d, 0.0, 1.0), out=img)
+    return img
+
+
+def piecewise_image(shape: Tuple[int, int] = (225, 225), seed: int = 8) -> np.ndarray:
+    """8-bit-range piecewise-smooth image: a shaded background, 12 ellipses
+    and 6 rectangles of random grey levels, 20 small bright spots; clipped to
+    [0, 255]."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.arange(shape[0], dtype=np.float64), np.arange(shape[1], dtype=np.float64),
+                         indexing="ij")
+    img = 40.0 + 60.0 * (yy / shape[0]) + 30.0 * (xx / shape[1])
+    for _ in range(12):
+        cy, cx = rng.uniform(0, shape[0]), rng.uniform(0, shape[1])
+        ry, rx = rng.uniform(6, 40), rng.uniform(6, 40)
+        th = rng.uniform(0, np.pi)
+        u = ((yy - cy) * np.cos(th) + (xx - cx) * np.sin(th)) / ry
+        v = (-(yy - cy) * np.sin(th) + (xx - cx) * np.cos(th)) / rx
+        img[u * u + v * v <= 1.0] = rng.uniform(0, 255)
+    for _ in range(6):
+        y0, x0 = rng.integers(0, shape[0] - 20), rng.integers(0, shape[1] - 20)
+        h, w = rng.integers(8, 40), rng.integers(8, 40)
+        img[y0:y0 + h, x0:x0 + w] = rng.uniform(0, 255)
+    for _ in range(20):
+        cy, cx = rng.uniform(0, shape[0]), rng.uniform(0, shape[1])
+        img = np.maximum(img, 255.0 * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * 1.5 ** 2)))
+    return np.clip(img, 0.0, 255.0)
+
+
+def gaussian_noise(blurred: np.ndarray, std: float, seed: int) -> np.ndarray:
+    """Y = blurred + N(0, std^2) white noise (float64)."""
+    rng = np.random.default_rng(seed)
+    b = np.asarray(blurred, dtype=np.float64)
+    return b + rng.normal(0.0, std, size=b.shape)
+
+
+# The two paper-shape workloads: (object, PSF extent, PSF sigma, noise std list).
+PAPER_2D = {
+    # Fig. 1 stand-in: 512x512, nine crossing lines; the paper gives no PSF:
+    # a 9x9 Gaussian, sigma 2, is used; noise std 5.
+    "lines512": {"object": lambda: crossing_lines(), "psf": (9, 9), "sigma": (2.0, 2.0), "noise": (5.0,)},
+    # Fig. 2 stand-in: 225x225 8-bit image, 5x5 PSF (a Gaussian, sigma 1),
+    # noise std 20 and 5.
+    "image225": {"object": lambda: piecewise_image(), "psf": (5, 5), "sigma": (1.0, 1.0), "noise": (20.0, 5.0)},
+}

@@ -167,3 +167,42 @@ def test_c3_deconv_steps_properties(nd, c3_deconv_inputs, prec):
     assert np.all(np.diff(f) < 0)
     assert float(xg.min()) >= 0.0
     assert abs(f[0] - f0) <= F0_TOL[prec] * f0
+
+
+# ---- the paper's two 2-D experiment shapes (synthetic stand-ins) ----------
+
+def snr_db(est, ref):
+    """SNR = 10 log10(||ref||^2 / ||est - ref||^2) over X's extent."""
+    ref = np.asarray(ref, np.float64)
+    return 10.0 * np.log10(np.sum(ref * ref) / np.sum((np.asarray(est, np.float64) - ref) ** 2))
+
+
+PAPER_CASES = [(name, std) for name, w in synth.PAPER_2D.items() for std in w["noise"]]
+
+
+@pytest.mark.parametrize("name,std", PAPER_CASES)
+def test_paper_2d_deconv_vs_oracle(nd, name, std):
+    """100 FP32 iterations from the blurred start X0 = max(crop(Y), 0) against
+    the FP64 oracle: same decisions, objective to 1e-5, X to 1e-4, SNR to
+    0.01 dB."""
+    say("case paper 2-D %s std %g" % (name, std))
+    w = synth.PAPER_2D[name]
+    x = w["object"]()
+    h = synth.gaussian_psf(w["psf"], w["sigma"])
+    y = synth.gaussian_noise(oracle.conv_full(x, h), std, seed=11)
+    p = [(e - 1) // 2 for e in w["psf"]]
+    x0 = np.maximum(y[p[0]:p[0] + x.shape[0], p[1]:p[1] + x.shape[1]], 0.0)
+    yg = torch.from_numpy(y.astype(np.float32)).cuda()
+    hg = torch.from_numpy(h.astype(np.float32)).cuda()
+    xg = torch.from_numpy(x0.astype(np.float32)).cuda()
+    xg, st, info = nd.deconv_iterate(yg, hg, xg, 100)
+    torch.cuda.synchronize()
+    xo, so, done, status = oracle.deconv(y.astype(np.float32).astype(np.float64), h.astype(np.float32),
+                                         x0.astype(np.float32).astype(np.float64), 100)
+    stg = st.cpu().numpy()
+    assert info.cpu().tolist() == [done, status] == [100, 0]
+    np.testing.assert_array_equal(stg[1:, 2], so[1:, 2])
+    assert np.all(np.abs(stg[:, 0] - so[:, 0]) <= 1e-5 * np.abs(so[:, 0]))
+    xe = xg.cpu().numpy()
+    assert rel_l2(xe, xo) <= 1e-4
+    assert abs(snr_db(xe, x) - snr_db(xo, x)) <= 0.01
