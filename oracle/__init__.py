@@ -256,32 +256,67 @@ def explicit_A(m, h):
     return sum(blocks)
 
 
-def objective(x, y, h, lam=0.0):
-    """f(X) = 1/2 ||A X - Y||_2^2 + lam/2 ||X||_2^2.  lam = 0 is the paper's
-    objective; lam > 0 is the identity (Tikhonov) weight this library adds."""
+def laplacian(ndim):
+    """The discrete Laplacian as a 3x..x3 stencil over `ndim` axes: -2*ndim at
+    the centre, +1 at the two neighbours along each axis, 0 elsewhere.  As a
+    PSF under the full convolution it is the operator L of the Tikhonov-Miller
+    term (zero outside X's box, no wrap), the regularised family the paper's
+    introduction names."""
+    l = np.zeros((3,) * ndim)
+    c = (1,) * ndim
+    l[c] = -2.0 * ndim
+    for ax in range(ndim):
+        for d in (0, 2):
+            idx = list(c)
+            idx[ax] = d
+            l[tuple(idx)] = 1.0
+    return l
+
+
+def objective(x, y, h, lam=0.0, mu=0.0):
+    """f(X) = 1/2 ||A X - Y||_2^2 + lam/2 ||X||_2^2 + mu/2 ||L X||_2^2.
+    lam = mu = 0 is the paper's objective; lam is the identity (Tikhonov)
+    weight and mu the Laplacian (Tikhonov-Miller) weight this library adds."""
     r = conv_full(x, h) - _d(y)
     x = _d(x)
-    return 0.5 * float(np.sum(r * r)) + 0.5 * lam * float(np.sum(x * x))
+    f = 0.5 * float(np.sum(r * r)) + 0.5 * lam * float(np.sum(x * x))
+    if mu:
+        lx = conv_full(x, laplacian(x.ndim))
+        f += 0.5 * mu * float(np.sum(lx * lx))
+    return f
 
 
-def initial_delta(h, lam=0.0):
-    """delta_0 = 1/(||h||_1^2 + lam).  The paper fixes no initial step; since
-    ||A||_2 <= ||h||_1 (Young's inequality) this is at most 1/L for the
-    gradient's Lipschitz constant L, so a first trial fails the decrease test
-    only at a stationary point."""
-    return 1.0 / (float(np.sum(np.abs(_d(h)))) ** 2 + lam)
+def initial_delta(h, lam=0.0, mu=0.0):
+    """delta_0 = 1/(||h||_1^2 + lam + mu ||l||_1^2).  The paper fixes no
+    initial step; since ||A||_2 <= ||h||_1 (Young's inequality) this is at
+    most 1/L for the gradient's Lipschitz constant L, so a first trial fails
+    the decrease test only at a stationary point.  ||l||_1 = 4n for the
+    Laplacian over n axes."""
+    h = _d(h)
+    l1 = 4.0 * h.ndim if mu else 0.0
+    return 1.0 / (float(np.sum(np.abs(h))) ** 2 + lam + mu * l1 * l1)
+
+
+def gradient(x, y, h, lam=0.0, mu=0.0):
+    """grad f = A^T (A X - Y) + lam X + mu L^T L X (the fused form of Eq. 6)."""
+    x = _d(x)
+    g = conv_adjoint(conv_full(x, h) - _d(y), h) + lam * x
+    if mu:
+        l = laplacian(x.ndim)
+        g = g + mu * conv_adjoint(conv_full(x, l), l)
+    return g
 
 
 STEP_RULES = ("fixed", "cauchy", "bb")
 
 
-def first_trial(rule, g, h, lam, d0, s_prev=None, g_prev=None):
+def first_trial(rule, g, h, lam, d0, s_prev=None, g_prev=None, mu=0.0):
     """First trial step of one iteration.  The paper's rule only demands that
     the accepted delta_k decreases f; the first trial is free:
 
       fixed:  delta_0 = 1/(||h||_1^2 + lam) every iteration;
       cauchy: the exact line minimiser along -g of the unprojected objective,
-              <g,g> / (||A g||^2 + lam ||g||^2);
+              <g,g> / (||A g||^2 + lam ||g||^2 + mu ||L g||^2);
       bb:     Barzilai-Borwein, <s,s> / <s,y> with s = X^k - X^{k-1} and
               y = g^k - g^{k-1} (delta_0 on the first iteration).
 
@@ -292,6 +327,9 @@ def first_trial(rule, g, h, lam, d0, s_prev=None, g_prev=None):
         ag = conv_full(g, h)
         num = float(np.sum(g * g))
         den = float(np.sum(ag * ag)) + lam * num
+        if mu:
+            lg = conv_full(g, laplacian(g.ndim))
+            den += mu * float(np.sum(lg * lg))
     elif rule == "bb":
         if s_prev is None:
             return d0
@@ -303,7 +341,7 @@ def first_trial(rule, g, h, lam, d0, s_prev=None, g_prev=None):
     return q if np.isfinite(q) and q > 0 else d0
 
 
-def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None, rule="fixed"):
+def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None, rule="fixed", mu=0.0):
     """Non-negative projected gradient of the section "Application to
     2-dimensional deconvolution", applied to any n:
 
@@ -318,16 +356,17 @@ def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None, ru
     If no trial decreases f, or f becomes non-finite, the loop stops early.
     With deltas given (one per step) the steps are replayed with those values
     and no test.  `rule` picks the first trial of each iteration (see
-    first_trial); the halving that follows is the same for every rule.
+    first_trial); the halving that follows is the same for every rule.  mu
+    adds the Laplacian term mu/2 ||L X||^2 to f (and mu L^T L X to g).
 
     Returns (X, stats, iters_done, status): stats rows (f_k, delta_k,
     rejections_k, ||X^{k+1}-X^k||_2), row 0 holding f(X^0); status 0 for a
     full run, 1 for no descent, 2 for a non-finite objective."""
     y, h = _d(y), _d(h)
     x = _d(x0).copy()
-    f_k = objective(x, y, h, lam)
+    f_k = objective(x, y, h, lam, mu)
     stats = [(f_k, np.nan, 0.0, np.nan)]
-    d0 = initial_delta(h, lam)
+    d0 = initial_delta(h, lam, mu)
     done, status = 0, 0
     s_prev = g_prev = None
     if not np.isfinite(f_k):
@@ -338,17 +377,20 @@ def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None, ru
         else:
             g = conv_adjoint(conv_full(x, h) - y, h)
         g = g + lam * x
+        if mu:
+            lap = laplacian(x.ndim)
+            g = g + mu * conv_adjoint(conv_full(x, lap), lap)
         if deltas is not None:
             d = float(deltas[k])
             xt = np.maximum(x - d * g, 0.0)
-            f_t = objective(xt, y, h, lam)
+            f_t = objective(xt, y, h, lam, mu)
             stats.append((f_t, d, 0.0, float(np.linalg.norm(xt - x))))
             x, f_k, done = xt, f_t, done + 1
             continue
-        d, rej, accepted = first_trial(rule, g, h, lam, d0, s_prev, g_prev), 0, False
+        d, rej, accepted = first_trial(rule, g, h, lam, d0, s_prev, g_prev, mu), 0, False
         for _ in range(jmax):
             xt = np.maximum(x - d * g, 0.0)
-            f_t = objective(xt, y, h, lam)
+            f_t = objective(xt, y, h, lam, mu)
             if not np.isfinite(f_t):
                 status = 2
                 break

@@ -396,3 +396,58 @@ def test_bb_falls_back_without_curvature():
     assert oracle.first_trial("bb", g, h, 0.0, d0, np.zeros((4, 4)), g) == d0   # <s,y> = 0
     assert oracle.first_trial("bb", g, h, 0.0, d0, None, None) == d0            # first iteration
     assert oracle.first_trial("cauchy", np.zeros((4, 4)), h, 0.0, d0) == d0     # g = 0
+
+
+# ---- Tikhonov-Miller (Laplacian) term mu/2 ||L X||^2 ----
+
+def test_laplacian_stencil_is_the_second_difference():
+    """In 1-D, (L x)[i] over the full extent is x[i-2] - 2 x[i-1] + x[i]
+    (zero outside), i.e. the second difference centred at i-1."""
+    x = RNG.random(9)
+    lx = oracle.conv_full(x, oracle.laplacian(1))
+    xp = np.concatenate([[0.0, 0.0], x, [0.0, 0.0]])
+    ref = np.array([xp[i] - 2 * xp[i + 1] + xp[i + 2] for i in range(11)])
+    np.testing.assert_allclose(lx, ref, rtol=0, atol=1e-15)
+    l3 = oracle.laplacian(3)
+    assert l3.sum() == 0 and np.array_equal(l3, l3[::-1, ::-1, ::-1]) and np.abs(l3).sum() == 12
+
+
+@pytest.mark.parametrize("lam,mu", [(0.0, 0.2), (0.3, 0.05)])
+def test_gradient_matches_finite_differences_with_laplacian(lam, mu):
+    rng = np.random.default_rng(41)
+    h = rng.random((3, 3, 5))
+    x = rng.random((4, 5, 6))
+    y = oracle.conv_full(rng.random((4, 5, 6)), h)
+    g = oracle.gradient(x, y, h, lam, mu)
+    v = rng.standard_normal(x.shape)
+    eps = 1e-4
+    fd = (oracle.objective(x + eps * v, y, h, lam, mu) - oracle.objective(x - eps * v, y, h, lam, mu)) / (2 * eps)
+    assert abs(fd - float(np.sum(g * v))) <= 1e-7 * abs(fd)
+
+
+def test_laplacian_regularised_solution_closed_form():
+    """With the identity PSF the regularised objective is minimised by
+    X* = (I + mu L^T L)^{-1} Y; L is built as the dense matrix of the full
+    convolution (explicit_A, not conv_full) and Y is large enough that the
+    bound X >= 0 stays inactive."""
+    mu, m = 0.1, (5, 6)
+    y = 10.0 + RNG.random(m)
+    h = np.ones((1, 1))
+    L = oracle.explicit_A(m, oracle.laplacian(2))
+    xs = np.linalg.solve(np.eye(30) + mu * L.T @ L, y.ravel()).reshape(m)
+    # the loop runs until f stops decreasing in FP64 (status 1): ||X - X*||
+    # shrinks by (1 - delta_0) per step, about 1e-7 relative when it stops
+    x, st, done, status = oracle.deconv(y, h, np.full(m, 5.0), 300, mu=mu)
+    assert done >= 100 and status in (0, 1) and xs.min() > 0
+    np.testing.assert_allclose(x, xs, rtol=1e-6, atol=0)
+
+
+def test_initial_delta_bounds_the_curvature_with_laplacian():
+    """delta_0 <= 1 / lambda_max(A^T A + lam I + mu L^T L) (dense check)."""
+    rng = np.random.default_rng(42)
+    m, lam, mu = (4, 5), 0.2, 0.3
+    h = rng.random((3, 3))
+    A = oracle.explicit_A(m, h)
+    L = oracle.explicit_A(m, oracle.laplacian(2))
+    top = np.linalg.eigvalsh(A.T @ A + lam * np.eye(20) + mu * L.T @ L).max()
+    assert oracle.initial_delta(h, lam, mu) <= 1.0 / top
