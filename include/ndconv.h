@@ -117,24 +117,36 @@ NDC_API int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void
                    int iters, double lambda, int dtype, int precision, void *ws, size_t ws_bytes,
                    double *stats, int *info, void *stream);
 
-/* Step rules: the first trial of each iteration (the halving on failure and
- * the strict-decrease test that follow are those of deconv_iterate).  The
- * paper states only the acceptance rule f(X^{k+1}) < f(X^k) for delta_k
- * (Step 2 of its deconvolution algorithm), so any first trial is admissible:
- *   NDC_STEP_FIXED  delta_0 = 1/(||H||_1^2 + lambda)  (deconv_iterate);
- *   NDC_STEP_CAUCHY <g,g> / (||A g||^2 + lambda ||g||^2), the line minimiser of
- *                   the unprojected objective along -g; one extra forward
- *                   convolution per iteration;
- *   NDC_STEP_BB     Barzilai-Borwein <s,s>/<s,y>, s = X^k - X^{k-1},
- *                   y = g^k - g^{k-1}; delta_0 on the first iteration of a call.
- * A non-positive or non-finite quotient falls back to delta_0.
- * deconv_iterate_rule takes the arguments of deconv_iterate plus `rule`, with
- * the same workspace (deconv_workspace_bytes), outputs and error behaviour;
- * NDC_EINVAL for an unknown rule. */
+/* Extended deconvolution: the arguments of deconv_iterate plus
+ *   rule: the first trial of each iteration (the halving on failure and the
+ *         strict-decrease test that follow are those of deconv_iterate).
+ *         The paper states only the acceptance rule f(X^{k+1}) < f(X^k) for
+ *         delta_k (Step 2 of its deconvolution algorithm), so any first trial
+ *         is admissible:
+ *     NDC_STEP_FIXED  delta_0 (below), as deconv_iterate;
+ *     NDC_STEP_CAUCHY <g,g> / (||A g||^2 + lambda ||g||^2 + mu ||L g||^2), the
+ *                     line minimiser of the unprojected objective along -g;
+ *                     one extra forward convolution per iteration;
+ *     NDC_STEP_BB     Barzilai-Borwein <s,s>/<s,y>, s = X^k - X^{k-1},
+ *                     y = g^k - g^{k-1}; delta_0 on the first iteration of a
+ *                     call.  A non-positive or non-finite quotient falls back
+ *                     to delta_0.
+ *   mu:   weight of a Tikhonov-Miller term mu/2 ||L X||^2 (the regularised
+ *         family the paper's introduction names; >= 0, 0 = off).  L is the
+ *         full convolution by the discrete Laplacian over the problem's n
+ *         axes (3^n stencil: -2n at the centre, +1 at the axis neighbours;
+ *         zero outside X).  The gradient gains mu L^T L X and
+ *         delta_0 = 1/(||H||_1^2 + lambda + mu (4n)^2).
+ * With mu > 0 the workspace is deconv_workspace_bytes_ex(..., 1) (larger by
+ * two (m+2)-extent arrays, one X-sized array and the stencil); with mu = 0 it
+ * is deconv_workspace_bytes.  NDC_EINVAL for an unknown rule or a negative
+ * or non-finite mu; otherwise errors as deconv_iterate. */
 enum { NDC_STEP_FIXED = 0, NDC_STEP_CAUCHY = 1, NDC_STEP_BB = 2 };
-NDC_API int deconv_iterate_rule(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
-                                int iters, double lambda, int dtype, int precision, int rule, void *ws,
-                                size_t ws_bytes, double *stats, int *info, void *stream);
+NDC_API size_t deconv_workspace_bytes_ex(int n, const int64_t *m, const int64_t *p, int dtype, int precision,
+                                         int regularised);
+NDC_API int deconv_iterate_ex(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
+                              int iters, double lambda, double mu, int dtype, int precision, int rule, void *ws,
+                              size_t ws_bytes, double *stats, int *info, void *stream);
 
 /* Batched form: many independent 3-D volumes, each with its own extents m,
  * half-widths p and PSF, in persistent launches that walk one tile list for

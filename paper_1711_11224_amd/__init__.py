@@ -138,10 +138,11 @@ STEP_RULES = {"fixed": 0, "cauchy": 1, "bb": 2}
 
 
 def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=None, info=None, stream=None,
-                   rule="fixed"):
+                   rule="fixed", mu=0.0):
     """Run `iters` accepted projected-gradient steps in place on X (Steps 1-3,
     delta accepted by f(X^{k+1}) < f(X^k)).  `rule` picks the first trial of
-    each iteration: "fixed" (delta_0), "cauchy" or "bb" (see ndconv.h).
+    each iteration: "fixed" (delta_0), "cauchy" or "bb"; `mu` weights the
+    Laplacian (Tikhonov-Miller) term mu/2 ||L X||^2 (see ndconv.h).
     Returns (X, stats, info) with stats (iters+1, 4) float64 and info (2,)
     int32 on the device."""
     if rule not in STEP_RULES:
@@ -154,21 +155,21 @@ def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=N
     if list(Y.shape) != [a + 2 * b for a, b in zip(X.shape, p)]:
         raise ValueError("Y must have extent m+2p")
     n, mm, pp, dt, pr = X.dim(), i64_array(X.shape), i64_array(p), _dtype_code(X), _prec(precision)
-    need = lib.deconv_workspace_bytes(n, mm, pp, dt, pr)
+    need = lib.deconv_workspace_bytes_ex(n, mm, pp, dt, pr, 1 if mu > 0 else 0)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=X.device)
     if stats is None:
         stats = torch.full((iters + 1, 4), float("nan"), dtype=torch.float64, device=X.device)
     if info is None:
         info = torch.zeros(2, dtype=torch.int32, device=X.device)
-    if rule == "fixed":
+    if rule == "fixed" and mu == 0:
         check(lib.deconv_iterate(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam), dt, pr,
                                  ws.data_ptr(), ws.numel() * ws.element_size(), stats.data_ptr(), info.data_ptr(),
                                  _stream(stream)), "deconv_iterate")
     else:
-        check(lib.deconv_iterate_rule(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam),
-                                      dt, pr, STEP_RULES[rule], ws.data_ptr(), ws.numel() * ws.element_size(),
-                                      stats.data_ptr(), info.data_ptr(), _stream(stream)), "deconv_iterate_rule")
+        check(lib.deconv_iterate_ex(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam),
+                                    float(mu), dt, pr, STEP_RULES[rule], ws.data_ptr(), ws.numel() * ws.element_size(),
+                                    stats.data_ptr(), info.data_ptr(), _stream(stream)), "deconv_iterate_ex")
     return X, stats, info
 
 
@@ -181,7 +182,7 @@ def conv_adjoint(r, h, precision="native"):
     return conv_adjoint_nd(r.contiguous(), h.contiguous(), precision=precision)
 
 
-def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed"):
+def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed", mu=0.0):
     """Projected-gradient deconvolution; x0 defaults to the flux-matching flat
     start max(sum Y, 0)/(N sum H).  Returns (x, stats, info)."""
     y, h = y.contiguous(), h.contiguous()
@@ -196,4 +197,4 @@ def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed"):
         x.fill_(float(val))
     else:
         x = x0.clone().contiguous()
-    return deconv_iterate(y, h, x, iters, lam=lam, precision=precision, rule=rule)
+    return deconv_iterate(y, h, x, iters, lam=lam, precision=precision, rule=rule, mu=mu)

@@ -14,7 +14,7 @@ NDC_F32, NDC_F64 = 0, 1
 NDC_PREC_NATIVE, NDC_PREC_BF16, NDC_PREC_SPLIT_BF16 = 0, 1, 2
 
 EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_dH_nd",
-           "deconv_workspace_bytes", "deconv_iterate", "deconv_iterate_rule", "ndc_batch_plan_create", "ndc_batch_plan_destroy",
+           "deconv_workspace_bytes", "deconv_iterate", "deconv_workspace_bytes_ex", "deconv_iterate_ex", "ndc_batch_plan_create", "ndc_batch_plan_destroy",
            "ndc_batch_workspace_bytes", "ndc_batch_plan_info", "ndc_batch_conv_full", "ndc_batch_conv_adjoint",
            "ndc_batch_deconv", "ndc_strerror", "ndc_version")
 
@@ -45,9 +45,11 @@ def _load():
     lib.deconv_iterate.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, ctypes.c_double, c_int, c_int,
                                    vp, sz, vp, vp, vp]
     lib.deconv_iterate.restype = c_int
-    lib.deconv_iterate_rule.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, ctypes.c_double, c_int, c_int, c_int,
-                                        vp, sz, vp, vp, vp]
-    lib.deconv_iterate_rule.restype = c_int
+    lib.deconv_workspace_bytes_ex.argtypes = [c_int, i64p, i64p, c_int, c_int, c_int]
+    lib.deconv_workspace_bytes_ex.restype = sz
+    lib.deconv_iterate_ex.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, ctypes.c_double, ctypes.c_double, c_int,
+                                      c_int, c_int, vp, sz, vp, vp, vp]
+    lib.deconv_iterate_ex.restype = c_int
     pvp = ctypes.POINTER(ctypes.c_void_p)
     lib.ndc_batch_plan_create.argtypes = [c_int, i64p, i64p, c_int, c_int, ctypes.POINTER(c_int), pvp]
     lib.ndc_batch_plan_create.restype = c_int

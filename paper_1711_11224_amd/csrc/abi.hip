@@ -11,9 +11,10 @@
 
 namespace ndc {
 
-size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision);
+size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision, int reg_ndim);
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
-               double lambda, int dtype, int precision, void *ws, double *stats, int *info, int rule, hipStream_t s);
+               double lambda, double mu, int ndim, int dtype, int precision, void *ws, double *stats, int *info,
+               int rule, hipStream_t s);
 bool mfma_supported(const Geom &g, int dtype, int precision);
 bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype);
 size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype);
@@ -301,19 +302,27 @@ int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const v
 size_t deconv_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype, int precision) {
   Extents E;
   if (prepare(n, m, p, dtype, precision, E)) return 0;
-  return deconv_ws_bytes(E.m3, E.p3, dtype, precision);
+  return deconv_ws_bytes(E.m3, E.p3, dtype, precision, 0);
+}
+
+size_t deconv_workspace_bytes_ex(int n, const int64_t *m, const int64_t *p, int dtype, int precision,
+                                 int regularised) {
+  Extents E;
+  if (prepare(n, m, p, dtype, precision, E)) return 0;
+  return deconv_ws_bytes(E.m3, E.p3, dtype, precision, regularised ? n : 0);
 }
 
 static int deconv_checked(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
-                          int iters, double lambda, int dtype, int precision, int rule, void *ws, size_t ws_bytes,
-                          double *stats, int *info, void *stream) {
+                          int iters, double lambda, double mu, int dtype, int precision, int rule, void *ws,
+                          size_t ws_bytes, double *stats, int *info, void *stream) {
   if (rule != NDC_STEP_FIXED && rule != NDC_STEP_CAUCHY && rule != NDC_STEP_BB) return NDC_EINVAL;
+  if (!(mu >= 0.0) || !isfinite(mu)) return NDC_EINVAL;
   Extents E;
   int rc = prepare(n, m, p, dtype, precision, E);
   if (rc) return rc;
   if (!Y || !H || !X) return NDC_EINVAL;
   if (iters < 0 || !(lambda >= 0.0) || !isfinite(lambda)) return NDC_EINVAL;
-  const size_t need = deconv_ws_bytes(E.m3, E.p3, dtype, precision);
+  const size_t need = deconv_ws_bytes(E.m3, E.p3, dtype, precision, mu > 0.0 ? n : 0);
   if (!ws || ws_bytes < need) return NDC_EWORKSPACE;
   const size_t es = esize(dtype);
   const size_t ns = stats ? (size_t)4 * ((size_t)iters + 1) * sizeof(double) : 0;
@@ -328,21 +337,21 @@ static int deconv_checked(int n, const int64_t *m, const int64_t *p, const void 
   }
   if (!device_ptr(Y) || !device_ptr(H) || !device_ptr(X) || !device_ptr(ws)) return NDC_EINVAL;
   if ((stats && !device_ptr(stats)) || (info && !device_ptr(info))) return NDC_EINVAL;
-  return deconv_run(E.m3, E.p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, rule,
+  return deconv_run(E.m3, E.p3, Y, H, X, iters, lambda, mu, n, dtype, precision, ws, stats, info, rule,
                     (hipStream_t)stream);
 }
 
 int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
                    double lambda, int dtype, int precision, void *ws, size_t ws_bytes, double *stats, int *info,
                    void *stream) {
-  return deconv_checked(n, m, p, Y, H, X, iters, lambda, dtype, precision, NDC_STEP_FIXED, ws, ws_bytes, stats,
-                        info, stream);
+  return deconv_checked(n, m, p, Y, H, X, iters, lambda, 0.0, dtype, precision, NDC_STEP_FIXED, ws, ws_bytes,
+                        stats, info, stream);
 }
 
-int deconv_iterate_rule(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
-                        double lambda, int dtype, int precision, int rule, void *ws, size_t ws_bytes, double *stats,
-                        int *info, void *stream) {
-  return deconv_checked(n, m, p, Y, H, X, iters, lambda, dtype, precision, rule, ws, ws_bytes, stats, info,
+int deconv_iterate_ex(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
+                      double lambda, double mu, int dtype, int precision, int rule, void *ws, size_t ws_bytes,
+                      double *stats, int *info, void *stream) {
+  return deconv_checked(n, m, p, Y, H, X, iters, lambda, mu, dtype, precision, rule, ws, ws_bytes, stats, info,
                         stream);
 }
 

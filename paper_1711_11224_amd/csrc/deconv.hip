@@ -17,6 +17,13 @@
 //   1b. forward of G with the NORM epilogue      (NEW, Cauchy): ||A g||^2
 //   1c. step (one work-group): delta from the rule, phase -> RETRY
 // and steps 2-5 follow as for a halved retry.
+//
+// With the Tikhonov-Miller term mu/2 ||L X||^2 (L: full convolution by the
+// 3^n Laplacian stencil, through the same operators) the step also runs
+//   0. transpose of P = L X^k by the stencil      (NEW):  Q = L^T L X^k
+//      (the gradient epilogues add mu*Q)
+//   3b. forward of X_t by the stencil, SQR        (NEW|RETRY): P_t, ||P_t||^2
+// and commit also moves P <- P_t; f and the decision include mu/2 ||P||^2.
 #include <math.h>
 
 #include "ndc_device.h"
@@ -46,13 +53,14 @@ __device__ double wg_sum(const double *part, int64_t cnt, int comp, double (*red
 
 template <typename T>
 __global__ __launch_bounds__(ET) void init_kernel(const T *__restrict__ H, int64_t nh, double lambda, int iters,
-                                                  int jmax, int rule, DState *st) {
+                                                  int jmax, int rule, double mu, int ndim, DState *st) {
   __shared__ double red[ET / 64][2];
   double s = 0.0, dummy = 0.0;
   for (int64_t i = threadIdx.x; i < nh; i += ET) s += fabs((double)H[i]);
   block_sum2(s, dummy, red);
   if (threadIdx.x == 0) {
-    st->delta0 = 1.0 / (s * s + lambda);
+    const double l1 = 4.0 * ndim;  // ||Laplacian stencil||_1
+    st->delta0 = 1.0 / (s * s + lambda + mu * l1 * l1);
     st->delta = st->delta0;
     st->lambda = lambda;
     st->f_cur = 0.0;
@@ -65,7 +73,21 @@ __global__ __launch_bounds__(ET) void init_kernel(const T *__restrict__ H, int64
     st->accepted = 0;
     st->rule = rule;
     st->ss = 0.0;
+    st->mu = mu;
   }
+}
+
+// The 3^n Laplacian stencil over the problem's n axes, embedded in the folded
+// 3-D extent (k3 = 2 p3 + 1 with p3 = 1 on those axes, 0 on the leading ones):
+// -2n at the centre, +1 at the two neighbours along each axis.
+template <typename T>
+__global__ void laplacian_kernel(T *__restrict__ l, int kz, int ky, int kx, int ndim) {
+  const int e = threadIdx.x;
+  if (e >= kz * ky * kx) return;
+  const int a = e / (ky * kx), b = (e / kx) % ky, c = e % kx;
+  const int da = a - kz / 2, db = b - ky / 2, dc = c - kx / 2;
+  const int off = (da != 0) + (db != 0) + (dc != 0);
+  l[e] = off == 0 ? (T)(-2 * ndim) : (off == 1 ? (T)1 : (T)0);
 }
 
 template <typename T>
@@ -79,17 +101,19 @@ __global__ __launch_bounds__(ET) void zero_kernel(T *__restrict__ a, T *__restri
 // First trial of a Cauchy / BB iteration from the gradient partials (GRAD
 // epilogue: <g,g>, <s, g - g_old>) and, for Cauchy, ||A g||^2 (NORM epilogue).
 __global__ __launch_bounds__(ET) void step_kernel(DState *st, const double *part_grad, int64_t ng,
-                                                  const double *part_ag, int64_t na) {
+                                                  const double *part_ag, int64_t na, const double *part_lg,
+                                                  int64_t nl) {
   if (st->phase != PH_NEW) return;
   __shared__ double red[ET / 64][2];
   const double gg = wg_sum(part_grad, ng, 0, red);
   const double sy = wg_sum(part_grad, ng, 1, red);
   const double ag = st->rule == NDC_STEP_CAUCHY ? wg_sum(part_ag, na, 0, red) : 0.0;
+  const double lg = (st->rule == NDC_STEP_CAUCHY && nl) ? wg_sum(part_lg, nl, 0, red) : 0.0;
   if (threadIdx.x != 0) return;
   double num = 0.0, den = 0.0;
   if (st->rule == NDC_STEP_CAUCHY) {
     num = gg;
-    den = ag + st->lambda * gg;
+    den = ag + st->lambda * gg + st->mu * lg;
   } else if (st->k > 0) {  // BB; delta_0 on the first iteration of a call
     num = st->ss;
     den = sy;
@@ -115,12 +139,14 @@ __global__ __launch_bounds__(ET) void sumsq_kernel(const T *__restrict__ x, int6
 }
 
 __global__ __launch_bounds__(ET) void f0_kernel(DState *st, const double *part_fwd, int64_t nf,
-                                                const double *part_x, int64_t nx, double *stats, int *info) {
+                                                const double *part_x, int64_t nx, const double *part_reg,
+                                                int64_t nreg, double *stats, int *info) {
   __shared__ double red[ET / 64][2];
   const double r2 = wg_sum(part_fwd, nf, 0, red);
   const double x2 = wg_sum(part_x, nx, 0, red);
+  const double l2 = nreg ? wg_sum(part_reg, nreg, 0, red) : 0.0;
   if (threadIdx.x == 0) {
-    const double f0 = 0.5 * r2 + 0.5 * st->lambda * x2;
+    const double f0 = 0.5 * r2 + 0.5 * st->lambda * x2 + 0.5 * st->mu * l2;
     st->f_cur = f0;
     if (!isfinite(f0)) {
       st->status = NDC_ENONFINITE;
@@ -166,7 +192,8 @@ __global__ __launch_bounds__(ET) void update_kernel(const T *__restrict__ X, con
 
 __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *part_fwd, int64_t nf,
                                                     const double *part_upd, int64_t n_adj, int64_t n_ew,
-                                                    double *stats, int *info) {
+                                                    const double *part_reg, int64_t nreg, double *stats,
+                                                    int *info) {
   const int phase = st->phase;  // uniform
   if (phase == PH_DONE) {
     if (threadIdx.x == 0) st->accepted = 0;
@@ -177,8 +204,9 @@ __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *pa
   const double r2 = wg_sum(part_fwd, nf, 0, red);
   const double x2 = wg_sum(part_upd, nu, 0, red);
   const double dx2 = wg_sum(part_upd, nu, 1, red);
+  const double l2 = nreg ? wg_sum(part_reg, nreg, 0, red) : 0.0;
   if (threadIdx.x != 0) return;
-  const double ft = 0.5 * r2 + 0.5 * st->lambda * x2;
+  const double ft = 0.5 * r2 + 0.5 * st->lambda * x2 + 0.5 * st->mu * l2;
   if (!isfinite(ft)) {
     st->status = NDC_ENONFINITE;
     st->phase = PH_DONE;
@@ -218,23 +246,55 @@ __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *pa
 template <typename T>
 __global__ __launch_bounds__(ET) void commit_kernel(const DState *st, T *__restrict__ X, const T *__restrict__ Xt,
                                                     int64_t n, T *__restrict__ R, const T *__restrict__ Rt,
-                                                    int64_t ny, T *__restrict__ S) {
+                                                    int64_t ny, T *__restrict__ S, T *__restrict__ P,
+                                                    const T *__restrict__ Pt, int64_t np) {
   if (!st->accepted) return;
-  const int64_t m = n > ny ? n : ny;
+  int64_t m = n > ny ? n : ny;
+  if (P && np > m) m = np;
   for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < m; i += (int64_t)gridDim.x * ET) {
     if (i < n) {
       if (S) S[i] = Xt[i] - X[i];  // BB: the accepted step
       X[i] = Xt[i];
     }
     if (i < ny) R[i] = Rt[i];
+    if (P && i < np) P[i] = Pt[i];
   }
 }
 
 struct WsLayout {
-  size_t state, part_fwd, part_upd, xt, g, r, rt, sbuf, total;
+  size_t state, part_fwd, part_upd, xt, g, r, rt, sbuf;
+  size_t lap, part_reg, p, pt, q;  // Tikhonov-Miller term (when regularised)
+  size_t total;
 };
 
-WsLayout layout(int64_t N, int64_t NY, size_t esz, int64_t nf, int64_t nu) {
+// Tikhonov-Miller geometry: the 3^n Laplacian over the problem's last n of
+// the 3 folded axes (ndim = 0: no regularisation buffers).
+struct RegSizes {
+  int ndim;
+  int64_t pl3[3], NP, NL;
+  Geom gl, gla;
+  ConvPlan pl, pla;
+};
+
+RegSizes reg_sizes(const int64_t m3[3], int ndim, int dtype, int precision) {
+  RegSizes r{};
+  r.ndim = ndim;
+  if (!ndim) return r;
+  r.NP = 1;
+  r.NL = 1;
+  for (int i = 0; i < 3; ++i) {
+    r.pl3[i] = i >= 3 - ndim ? 1 : 0;
+    r.NP *= m3[i] + 2 * r.pl3[i];
+    r.NL *= 2 * r.pl3[i] + 1;
+  }
+  r.gl = forward_geom(m3, r.pl3);
+  r.gla = adjoint_geom(m3, r.pl3);
+  r.pl = plan_conv(r.gl, dtype, precision);
+  r.pla = plan_conv(r.gla, dtype, precision);
+  return r;
+}
+
+WsLayout layout(int64_t N, int64_t NY, size_t esz, int64_t nf, int64_t nu, const RegSizes &R) {
   WsLayout L;
   size_t o = 0;
   L.state = o;
@@ -253,6 +313,19 @@ WsLayout layout(int64_t N, int64_t NY, size_t esz, int64_t nf, int64_t nu) {
   o += align256((size_t)NY * esz);
   L.sbuf = o;  // accepted step X^k - X^{k-1} (Barzilai-Borwein rule)
   o += align256((size_t)N * esz);
+  L.lap = L.part_reg = L.p = L.pt = L.q = 0;
+  if (R.ndim) {
+    L.lap = o;
+    o += align256((size_t)R.NL * esz);
+    L.part_reg = o;
+    o += align256((size_t)R.pl.nblocks * 2 * sizeof(double));
+    L.p = o;  // L X^k
+    o += align256((size_t)R.NP * esz);
+    L.pt = o;  // L X_t
+    o += align256((size_t)R.NP * esz);
+    L.q = o;  // L^T L X^k
+    o += align256((size_t)N * esz);
+  }
   L.total = o;
   return L;
 }
@@ -279,18 +352,26 @@ Sizes sizes_for(const int64_t m3[3], const int64_t p3[3], int dtype, int precisi
 
 template <typename T>
 int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *Xv, int iters,
-             double lambda, int dtype, int precision, void *ws, double *stats, int *info, int rule, hipStream_t s) {
+             double lambda, double mu, int ndim, int dtype, int precision, void *ws, double *stats, int *info,
+             int rule, hipStream_t s) {
   const Sizes S = sizes_for(m3, p3, dtype, precision);
+  const RegSizes RS = reg_sizes(m3, mu > 0.0 ? ndim : 0, dtype, precision);
   const int64_t nu = S.pa.nblocks > S.n_ew ? S.pa.nblocks : S.n_ew;
-  const WsLayout L = layout(S.N, S.NY, sizeof(T), S.pf.nblocks, nu);
+  const WsLayout L = layout(S.N, S.NY, sizeof(T), S.pf.nblocks, nu, RS);
   char *w = (char *)ws;
   DState *st = (DState *)(w + L.state);
   double *part_fwd = (double *)(w + L.part_fwd);
   double *part_upd = (double *)(w + L.part_upd);
   T *X = (T *)Xv, *Xt = (T *)(w + L.xt), *G = (T *)(w + L.g), *R = (T *)(w + L.r), *Rt = (T *)(w + L.rt);
   T *Sb = rule == NDC_STEP_BB ? (T *)(w + L.sbuf) : nullptr;
+  const bool reg = RS.ndim > 0;
+  T *lap = reg ? (T *)(w + L.lap) : nullptr, *P = reg ? (T *)(w + L.p) : nullptr;
+  T *Pt = reg ? (T *)(w + L.pt) : nullptr, *Q = reg ? (T *)(w + L.q) : nullptr;
+  double *part_reg = reg ? (double *)(w + L.part_reg) : nullptr;
+  const int64_t nreg = reg ? RS.pl.nblocks : 0;
 
-  hipLaunchKernelGGL(init_kernel<T>, dim3(1), dim3(ET), 0, s, (const T *)H, S.NH, lambda, iters, 30, rule, st);
+  hipLaunchKernelGGL(init_kernel<T>, dim3(1), dim3(ET), 0, s, (const T *)H, S.NH, lambda, iters, 30, rule,
+                     reg ? mu : 0.0, ndim, st);
   if (Sb) hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, Sb, G, S.N);
   hipLaunchKernelGGL(sumsq_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, S.N, part_upd);
   Epi ef{};
@@ -299,8 +380,16 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   ef.part = part_fwd;
   ef.phase = nullptr;
   if (launch_conv(S.pf, S.gf, dtype, precision, X, H, R, ef, s) != hipSuccess) return NDC_EDEVICE;
+  Epi el{};  // P = L X with ||P||^2 (initial point, then every trial)
+  el.mode = EPI_SQR;
+  el.part = part_reg;
+  if (reg) {
+    hipLaunchKernelGGL(laplacian_kernel<T>, dim3(1), dim3(64), 0, s, lap, (int)RS.gl.kz, (int)RS.gl.ky,
+                       (int)RS.gl.kx, ndim);
+    if (launch_conv(RS.pl, RS.gl, dtype, NDC_PREC_NATIVE, X, lap, P, el, s) != hipSuccess) return NDC_EDEVICE;
+  }
   hipLaunchKernelGGL(f0_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_fwd, S.pf.nblocks,
-                     (const double *)part_upd, S.n_ew, stats, info);
+                     (const double *)part_upd, S.n_ew, (const double *)part_reg, nreg, stats, info);
   if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
 
   Epi ea{};
@@ -312,6 +401,8 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   ea.part = part_upd;
   ea.phase = &st->phase;
   ea.phase_mask = 1 << PH_NEW;
+  ea.Q = Q;
+  ea.mu = mu;
   Epi eg{};  // Cauchy / BB: gradient first
   eg.mode = EPI_GRAD;
   eg.X = X;
@@ -320,39 +411,60 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   eg.phase = &st->phase;
   eg.phase_mask = 1 << PH_NEW;
   eg.S = Sb;
+  eg.Q = Q;
+  eg.mu = mu;
   Epi en{};  // Cauchy: ||A g||^2
   en.mode = EPI_NORM;
   en.part = part_fwd;
   en.phase = &st->phase;
   en.phase_mask = 1 << PH_NEW;
+  Epi enl = en;  // Cauchy with the Laplacian: ||L g||^2
+  enl.part = part_reg;
+  Epi eq{};  // Q = L^T P at the start of a step
+  eq.mode = EPI_STORE;
+  eq.phase = &st->phase;
+  eq.phase_mask = 1 << PH_NEW;
   Epi et{};
   et.mode = EPI_RESID;
   et.Y = Y;
   et.part = part_fwd;
   et.phase = &st->phase;
   et.phase_mask = (1 << PH_NEW) | (1 << PH_RETRY);
-  const int64_t ncommit = ew_blocks(S.NY > S.N ? S.NY : S.N);
+  Epi elt = el;  // P_t = L X_t for every trial
+  elt.phase = &st->phase;
+  elt.phase_mask = (1 << PH_NEW) | (1 << PH_RETRY);
+  int64_t ncm = S.NY > S.N ? S.NY : S.N;
+  if (reg && RS.NP > ncm) ncm = RS.NP;
+  const int64_t ncommit = ew_blocks(ncm);
 
   int remaining = iters;
   while (remaining > 0) {
     for (int step = 0; step < remaining; ++step) {
+      if (reg && launch_conv(RS.pla, RS.gla, dtype, NDC_PREC_NATIVE, P, lap, Q, eq, s) != hipSuccess)
+        return NDC_EDEVICE;
       if (rule == NDC_STEP_FIXED) {
         if (launch_conv(S.pa, S.ga, dtype, precision, R, H, Xt, ea, s) != hipSuccess) return NDC_EDEVICE;
       } else {
         if (launch_conv(S.pa, S.ga, dtype, precision, R, H, G, eg, s) != hipSuccess) return NDC_EDEVICE;
-        // (NORM stores nothing; R_t is passed as a valid, unused output)
+        // (NORM stores nothing; R_t / P_t are passed as valid, unused outputs)
         if (rule == NDC_STEP_CAUCHY && launch_conv(S.pf, S.gf, dtype, precision, G, H, Rt, en, s) != hipSuccess)
           return NDC_EDEVICE;
+        if (rule == NDC_STEP_CAUCHY && reg &&
+            launch_conv(RS.pl, RS.gl, dtype, NDC_PREC_NATIVE, G, lap, Pt, enl, s) != hipSuccess)
+          return NDC_EDEVICE;
         hipLaunchKernelGGL(step_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_upd, S.pa.nblocks,
-                           (const double *)part_fwd, S.pf.nblocks);
+                           (const double *)part_fwd, S.pf.nblocks, (const double *)part_reg, nreg);
       }
       hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, (const T *)G, Xt,
                          S.N, (const DState *)st, part_upd);
       if (launch_conv(S.pf, S.gf, dtype, precision, Xt, H, Rt, et, s) != hipSuccess) return NDC_EDEVICE;
+      if (reg && launch_conv(RS.pl, RS.gl, dtype, NDC_PREC_NATIVE, Xt, lap, Pt, elt, s) != hipSuccess)
+        return NDC_EDEVICE;
       hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_fwd, S.pf.nblocks,
-                         (const double *)part_upd, S.pa.nblocks, S.n_ew, stats, info);
+                         (const double *)part_upd, S.pa.nblocks, S.n_ew, (const double *)part_reg, nreg, stats,
+                         info);
       hipLaunchKernelGGL(commit_kernel<T>, dim3((unsigned)ncommit), dim3(ET), 0, s, (const DState *)st, X,
-                         (const T *)Xt, S.N, R, (const T *)Rt, S.NY, Sb);
+                         (const T *)Xt, S.N, R, (const T *)Rt, S.NY, Sb, P, (const T *)Pt, reg ? RS.NP : 0);
       if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
     }
     DState h;
@@ -366,18 +478,20 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
 
 }  // namespace
 
-size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision) {
+size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision, int reg_ndim) {
   const Sizes S = sizes_for(m3, p3, dtype, precision);
+  const RegSizes RS = reg_sizes(m3, reg_ndim, dtype, precision);
   const int64_t nu = S.pa.nblocks > S.n_ew ? S.pa.nblocks : S.n_ew;
   const size_t esz = dtype == NDC_F64 ? sizeof(double) : sizeof(float);
-  return layout(S.N, S.NY, esz, S.pf.nblocks, nu).total;
+  return layout(S.N, S.NY, esz, S.pf.nblocks, nu, RS).total;
 }
 
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
-               double lambda, int dtype, int precision, void *ws, double *stats, int *info, int rule, hipStream_t s) {
+               double lambda, double mu, int ndim, int dtype, int precision, void *ws, double *stats, int *info,
+               int rule, hipStream_t s) {
   if (dtype == NDC_F64)
-    return deconv_t<double>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, rule, s);
-  return deconv_t<float>(m3, p3, Y, H, X, iters, lambda, dtype, precision, ws, stats, info, rule, s);
+    return deconv_t<double>(m3, p3, Y, H, X, iters, lambda, mu, ndim, dtype, precision, ws, stats, info, rule, s);
+  return deconv_t<float>(m3, p3, Y, H, X, iters, lambda, mu, ndim, dtype, precision, ws, stats, info, rule, s);
 }
 
 }  // namespace ndc

@@ -30,16 +30,21 @@ __device__ inline void apply_epilogue(T *out, int64_t idx, T acc, const Epi &ep,
     out[idx] = r;
     s0 += (double)r * (double)r;
   } else if (ep.mode == EPI_GRAD) {
-    const T g = acc + (T)ep.lambda * ((const T *)ep.X)[idx];
+    T g = acc + (T)ep.lambda * ((const T *)ep.X)[idx];
+    if (ep.Q) g += (T)ep.mu * ((const T *)ep.Q)[idx];
     const T g_old = out[idx];
     out[idx] = g;
     s0 += (double)g * (double)g;
     if (ep.S) s1 += (double)((const T *)ep.S)[idx] * ((double)g - (double)g_old);
   } else if (ep.mode == EPI_NORM) {
     s0 += (double)acc * (double)acc;
+  } else if (ep.mode == EPI_SQR) {
+    out[idx] = acc;
+    s0 += (double)acc * (double)acc;
   } else {
     const T x = ((const T *)ep.X)[idx];
-    const T gr = acc + (T)ep.lambda * x;
+    T gr = acc + (T)ep.lambda * x;
+    if (ep.Q) gr += (T)ep.mu * ((const T *)ep.Q)[idx];
     ((T *)ep.G)[idx] = gr;
     const T xt = proj_nonneg<T>(x - (T)(*ep.delta) * gr);
     out[idx] = xt;

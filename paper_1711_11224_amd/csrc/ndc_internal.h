@@ -22,7 +22,7 @@ struct Geom {
   int flip;              // Hc[t] = H[k-1-t] on every axis
 };
 
-enum EpiMode { EPI_STORE = 0, EPI_RESID = 1, EPI_UPDATE = 2, EPI_GRAD = 3, EPI_NORM = 4 };
+enum EpiMode { EPI_STORE = 0, EPI_RESID = 1, EPI_UPDATE = 2, EPI_GRAD = 3, EPI_NORM = 4, EPI_SQR = 5 };
 
 // Deconvolution phases kept on the device (see deconv.hip).
 enum Phase { PH_NEW = 0, PH_RETRY = 1, PH_DONE = 2 };
@@ -30,12 +30,13 @@ enum Phase { PH_NEW = 0, PH_RETRY = 1, PH_DONE = 2 };
 // Epilogue applied to each output value `acc` at flat index i:
 //   STORE : out[i] = acc
 //   RESID : r = acc - Y[i]; out[i] = r; part0 += r^2            (objective)
-//   UPDATE: g = acc + lambda*X[i]; G[i] = g;
+//   UPDATE: g = acc + lambda*X[i] (+ mu*Q[i] if Q); G[i] = g;
 //           xt = max(X[i] - delta*g, 0); out[i] = xt;
 //           part0 += xt^2, part1 += (xt - X[i])^2               (Step 2)
-//   GRAD  : g = acc + lambda*X[i]; g_old = out[i]; out[i] = g;
+//   GRAD  : g = acc + lambda*X[i] (+ mu*Q[i] if Q); g_old = out[i]; out[i] = g;
 //           part0 += g^2, part1 += S[i]*(g - g_old) if S          (first trials)
 //   NORM  : nothing stored; part0 += acc^2                      (||A g||^2)
+//   SQR   : out[i] = acc; part0 += acc^2                        (L X, ||L X||^2)
 // Partial sums are double, one pair per work-group, written without atomics.
 // If phase != nullptr the kernel runs only when (1 << *phase) & phase_mask.
 struct Epi {
@@ -49,6 +50,8 @@ struct Epi {
   const int *phase;
   int phase_mask;
   const void *S;  // GRAD: previous accepted step X^k - X^{k-1}, or null
+  const void *Q;  // UPDATE / GRAD: L^T L X (Tikhonov-Miller term), or null
+  double mu;      // its weight
 };
 
 struct DState {
@@ -65,6 +68,7 @@ struct DState {
   int accepted;    // 1 right after an accepting decision (commit copies)
   int rule;        // first trial of each iteration: NDC_STEP_FIXED / CAUCHY / BB
   double ss;       // BB: ||X^k - X^{k-1}||^2 of the last accepted step
+  double mu;       // Tikhonov-Miller weight (0: off)
 };
 
 // Launch descriptors --------------------------------------------------------

@@ -136,8 +136,18 @@ def test_batch_plan_argument_checks():
     lib.ndc_batch_plan_destroy(None)  # no-op
 
 
-def test_deconv_rule_rejects_unknown_rule():
-    """An unknown step rule is refused before any pointer is looked at."""
-    rc = lib.deconv_iterate_rule(3, I([4, 4, 4]), I([1, 1, 1]), None, None, None, 1, 0.0, F32, 0, 7, None, 0,
-                                 None, None, None)
-    assert rc == -1
+def test_deconv_ex_rejects_bad_rule_or_weight():
+    """An unknown step rule or a negative / non-finite Laplacian weight is
+    refused before any pointer is looked at."""
+    for rule, mu in ((7, 0.0), (0, -1.0), (1, float("nan")), (2, float("inf"))):
+        rc = lib.deconv_iterate_ex(3, I([4, 4, 4]), I([1, 1, 1]), None, None, None, 1, 0.0, mu, F32, 0, rule, None,
+                                   0, None, None, None)
+        assert rc == -1
+
+
+def test_deconv_workspace_grows_with_the_laplacian_term():
+    m, p = I([8, 9, 10]), I([1, 2, 3])
+    base = lib.deconv_workspace_bytes(3, m, p, F32, 0)
+    assert lib.deconv_workspace_bytes_ex(3, m, p, F32, 0, 0) == base
+    # two (m+2)-extent arrays and one X-sized array at least
+    assert lib.deconv_workspace_bytes_ex(3, m, p, F32, 0, 1) >= base + 4 * (2 * 10 * 11 * 12 + 8 * 9 * 10)

@@ -143,12 +143,13 @@ def test_errors_on_device(nd):
 
 
 # ---------------------------------------------------------------- deconvolution
-def _check_deconv(nd, y, h, x0, iters, lam, npdt, tol_x, tol_f, prec="native", rule="fixed", tol_d=1e-14):
+def _check_deconv(nd, y, h, x0, iters, lam, npdt, tol_x, tol_f, prec="native", rule="fixed", tol_d=1e-14,
+                  mu=0.0):
     xg, st, info = nd.deconv_iterate(gpu(y, npdt), gpu(h, npdt), gpu(x0, npdt), iters, lam=lam, precision=prec,
-                                     rule=rule)
+                                     rule=rule, mu=mu)
     torch.cuda.synchronize()
     xo, so, done, status = oracle.deconv(y.astype(np.float64), h.astype(np.float64), x0.astype(np.float64),
-                                         iters, lam=lam, rule=rule)
+                                         iters, lam=lam, rule=rule, mu=mu)
     inf = info.cpu().numpy()
     stg = st.cpu().numpy()
     assert int(inf[0]) == done and int(inf[1]) == status
@@ -239,6 +240,36 @@ def test_deconv_step_rules_fp32_long(nd, rule):
         assert xg.min().item() >= 0
         res[r] = stg[-1, 0]
     assert res[rule] < res["fixed"]
+
+
+@pytest.mark.parametrize("rule", ["fixed", "cauchy", "bb"])
+def test_deconv_laplacian_fp64(nd, rule):
+    """Tikhonov-Miller term mu/2 ||L X||^2 (2-D 5-point stencil) against the
+    oracle: 2-D FP64, 64x64 X, 9x9 PSF, 30 iterations."""
+    cfg = synth.CONFIGS["c1_2d_f64"]
+    say("case deconv laplacian %s fp64" % rule)
+    x_true = synth.make_objects(cfg)
+    h = synth.psf_for(cfg)
+    y = synth.add_noise(oracle.conv_full(x_true, h), cfg)
+    x0 = synth.flat_start(y, h, cfg.shape)
+    _check_deconv(nd, y, h, x0, 30, 0.0, np.float64, 1e-8, 1e-11, rule=rule, tol_d=1e-9, mu=0.05)
+
+
+def test_deconv_laplacian_fp64_1d(nd):
+    """1-D (3-tap stencil) with lambda and mu together."""
+    say("case deconv laplacian 1-D")
+    rng = np.random.default_rng(33)
+    h = synth.gaussian_psf([11], (2.0,))
+    y = oracle.conv_full(10.0 * rng.random(300), h) + 0.1 * rng.standard_normal(310)
+    _check_deconv(nd, y, h, np.full(300, 5.0), 25, 0.2, np.float64, 1e-8, 1e-11, tol_d=1e-9, mu=0.3)
+
+
+@pytest.mark.parametrize("rule", ["fixed", "cauchy", "bb"])
+def test_deconv_laplacian_fp32(nd, rule):
+    """3-D 7-point stencil through the small-PSF kernels, FP32, 8 iterations."""
+    say("case deconv laplacian %s fp32" % rule)
+    y, h, x0 = _rule_problem_fp32()
+    _check_deconv(nd, y, h, x0, 8, 0.0, np.float32, 1e-4, 1e-5, rule=rule, tol_d=1e-4, mu=0.05)
 
 
 def test_deconv_stops_without_descent(nd):
