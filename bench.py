@@ -215,6 +215,19 @@ def bench_step_rules(nd, torch, y, h, x0, ws, steps=10, fixed_max=60):
     ms_f, f_fixed, done_f = run("fixed", fixed_max)
     out = {"steps": steps, "fixed": {"ms_per_step": round(ms_f / max(done_f, 1), 3),
                                      "f_after_steps": float(f_fixed[min(steps, done_f)])}}
+    # the Laplacian (Tikhonov-Miller) term: extra small-PSF convolutions per step
+    x = x0.clone()
+    nbytes = nd.deconv_workspace_bytes_ex(list(x0.shape), list(h.shape), torch.float32, "native", 1)
+    ws_tm = torch.empty(nbytes, dtype=torch.uint8, device=x0.device)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _, st, info = nd.deconv_iterate(y, h, x, steps, ws=ws_tm, mu=1e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    out["fixed_laplacian_mu1e-3"] = {"ms_per_step": round(e0.elapsed_time(e1) / max(int(info.cpu()[0]), 1), 3),
+                                     "workspace_GB": round(nbytes / 1e9, 3)}
+    del ws_tm
     for rule in ("cauchy", "bb"):
         ms, f, done = run(rule, steps)
         target = f[-1]

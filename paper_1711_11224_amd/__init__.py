@@ -17,6 +17,7 @@ PRECISIONS = {"native": NDC_PREC_NATIVE, "fp32": NDC_PREC_NATIVE, "fp64": NDC_PR
               "bf16": NDC_PREC_BF16, "split_bf16": NDC_PREC_SPLIT_BF16}
 
 __all__ = ["conv_full_nd", "conv_adjoint_nd", "conv_dH_nd", "deconv_iterate", "deconv_workspace_bytes",
+           "deconv_workspace_bytes_ex",
            "conv_full", "conv_adjoint", "deconv", "NdcError", "strerror", "PRECISIONS"]
 
 
@@ -132,6 +133,14 @@ def deconv_workspace_bytes(shape, psf_shape, dtype=torch.float32, precision="nat
     p = [(e - 1) // 2 for e in psf_shape]
     dt = NDC_F64 if dtype == torch.float64 else NDC_F32
     return int(lib.deconv_workspace_bytes(len(shape), i64_array(shape), i64_array(p), dt, _prec(precision)))
+
+
+def deconv_workspace_bytes_ex(shape, psf_shape, dtype=torch.float32, precision="native", regularised=1):
+    """Workspace of deconv_iterate with the Laplacian term (mu > 0)."""
+    p = [(e - 1) // 2 for e in psf_shape]
+    dt = NDC_F64 if dtype == torch.float64 else NDC_F32
+    return int(lib.deconv_workspace_bytes_ex(len(shape), i64_array(shape), i64_array(p), dt, _prec(precision),
+                                             int(regularised)))
 
 
 STEP_RULES = {"fixed": 0, "cauchy": 1, "bb": 2}
