@@ -21,6 +21,10 @@ size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype);
 hipError_t launch_dh(const int64_t m3[3], const int64_t p3[3], int dtype, const void *X, const void *G, void *dH,
                      void *ws, hipStream_t s);
 ConvPlan plan_conv_mfma(const Geom &g, int dtype, int precision);
+bool mfma32_supported(const Geom &g, int dtype, int precision);
+ConvPlan plan_conv_mfma32(const Geom &g, int precision);
+hipError_t launch_conv_mfma32(const Geom &g, int precision, const void *in, const void *H, void *out,
+                              const Epi &ep, hipStream_t s);
 bool small_supported(const Geom &g, int dtype, int precision);
 int64_t small_blocks(const Geom &g);
 hipError_t launch_conv_small(const Geom &g, int dtype, const void *in, const void *H, void *out, const Epi &ep,
@@ -79,7 +83,9 @@ static int64_t grid_blocks(dim3 g) { return (int64_t)g.x * g.y * g.z; }
 
 // Variant choice: small PSFs (every axis <= 7 taps) are bound by HBM and
 // stream through conv_small; wider ones go to the matrix cores when the x
-// width fits the MFMA tile; everything else takes the general VALU kernel.
+// width fits the MFMA tile (the bf16 forms of rows 11..33 taps wide on the
+// 32x32x16 instruction, the rest on the 4x4 forms); everything else takes
+// the general VALU kernel.
 static bool use_small(const Geom &g, int dtype, int precision) {
   return g.kx <= 7 && g.ky <= 7 && g.kz <= 7 && small_supported(g, dtype, precision) && !getenv("NDC_FORCE_VALU");
 }
@@ -94,6 +100,7 @@ ConvPlan plan_conv(const Geom &g, int dtype, int precision) {
     pl.lds_bytes = 0;
     return pl;
   }
+  if (mfma32_supported(g, dtype, precision) && mfma_supported(g, dtype, precision)) return plan_conv_mfma32(g, precision);
   if (mfma_supported(g, dtype, precision)) return plan_conv_mfma(g, dtype, precision);
   ConvPlan pl;
   pl.variant = 0;
@@ -108,6 +115,7 @@ hipError_t launch_conv(const ConvPlan &pl, const Geom &g, int dtype, int precisi
                        void *out, const Epi &ep, hipStream_t s) {
   if (pl.variant == 1) return launch_conv_mfma(pl, g, dtype, precision, in, H, out, ep, s);
   if (pl.variant == 2) return launch_conv_small(g, dtype, in, H, out, ep, s);
+  if (pl.variant == 3) return launch_conv_mfma32(g, precision, in, H, out, ep, s);
   return launch_conv_valu(g, dtype, precision, in, H, out, ep, 1, g.kz, s);
 }
 

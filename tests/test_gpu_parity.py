@@ -93,6 +93,66 @@ def test_reduced_precision(nd, m, p, prec):
     assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[prec]
 
 
+# PSF rows of 11..33 taps take the 32x32x16 form in bf16 and split-bf16:
+# 3 and 4 Toeplitz chunks per row (kx 11, 17 / 19, 31, 33), 2, 3 and 4 x blocks
+# per wave with ragged x tails, several 64-row tiles, ky = 33, 2p >= m, z groups
+# with ragged tails, a 2-D problem (three of the four planes of a group idle),
+# and a 256^3 volume with >= 512 work-groups (the widest tiles).
+WIDE_CASES = [((9, 70, 130), (2, 16, 15)), ((5, 100, 64), (1, 5, 5)), ((3, 40, 250), (4, 3, 8)),
+              ((4, 30, 90), (2, 4, 9)), ((80, 150), (12, 16)), ((2, 10, 20), (1, 8, 12)),
+              ((6, 20, 256), (2, 2, 10)), ((256, 256, 256), (0, 1, 5))]
+
+
+@pytest.mark.parametrize("form", ["1", "0"], ids=["mfma32x32", "mfma4x4"])
+@pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
+@pytest.mark.parametrize("m,p", WIDE_CASES)
+def test_reduced_precision_wide_rows(nd, m, p, prec, form, monkeypatch):
+    """Both matrix-core forms of the bf16 operators on every case (the
+    library picks one by volume; NDC_MFMA32 forces it here)."""
+    monkeypatch.setenv("NDC_MFMA32", form)
+    say("case wide m=%s p=%s %s form %s" % (m, p, prec, form))
+    rng = np.random.default_rng(hash((m, p)) % 2**32)
+    h = rng.standard_normal([2 * q + 1 for q in p]).astype(np.float32)  # asymmetric, signed
+    x = rng.random(m).astype(np.float32)
+    y = nd.conv_full_nd(gpu(x, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
+    yo = oracle.conv_full(x, h)
+    assert y.shape == yo.shape
+    assert rel_l2(y, yo) <= TOL[prec]
+    r = rng.standard_normal(yo.shape).astype(np.float32)
+    g = nd.conv_adjoint_nd(gpu(r, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
+    assert g.shape == tuple(m)
+    assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 5e-2), ("split_bf16", 5e-4)])
+def test_deconv_reduced_precision_wide_rows(nd, prec, tol, monkeypatch):
+    """Five projected-gradient steps with the 32x32x16 operators (every
+    epilogue: residual, update, objective partial sums) against the FP64
+    oracle.  Each step moves X by delta*G with G from both operators, so the
+    iterate and f carry a few times the operators' relative error e; the
+    bound is 5e for each precision, as for f(X^0) at the metric size."""
+    monkeypatch.setenv("NDC_MFMA32", "1")
+    say("case deconv wide %s" % prec)
+    rng = np.random.default_rng(21)
+    m, p = (6, 40, 70), (2, 6, 12)
+    h = rng.random([2 * q + 1 for q in p]).astype(np.float32) + 0.1
+    h /= h.sum()
+    xt = rng.random(m)
+    y = (oracle.conv_full(xt, h) + 0.01 * rng.standard_normal([a + 2 * b for a, b in zip(m, p)])).astype(np.float32)
+    x0 = np.full(m, float(xt.mean()), dtype=np.float32)
+    xg, st, info = nd.deconv_iterate(gpu(y, np.float32), gpu(h, np.float32), gpu(x0, np.float32), 5, lam=0.01,
+                                     precision=prec)
+    torch.cuda.synchronize()
+    xo, so, done, status = oracle.deconv(y.astype(np.float64), h.astype(np.float64), x0.astype(np.float64), 5,
+                                         lam=0.01)
+    assert info.cpu().tolist() == [5, 0] and (done, status) == (5, 0)
+    f = st.cpu().numpy()[:, 0]
+    assert np.all(np.diff(f) < 0)
+    assert np.all(np.abs(f - so[:, 0]) <= tol * np.abs(so[:, 0]))
+    assert float(xg.min()) >= 0.0
+    assert rel_l2(xg.cpu().numpy(), xo) <= tol
+
+
 # dH cases: one and several 128-column / 16-row tiles with ragged tails, PSF
 # rows or columns spanning several 24-wide blocks, 1x1x1 PSF, 1-D and 2-D
 DH_CASES = [((6, 9, 11), (1, 2, 3)), ((16, 40, 40), (3, 2, 4)), ((20, 33), (2, 5)),
