@@ -415,8 +415,14 @@ def main():
     if not args.no_precisions:
         for pr in ("fp32", "bf16", "split_bf16"):
             fm, am = time_pairs(nd, torch, x, h, pr, 3)
+            slow = 2.0 * N * K / (max(fm, am) * 1e-3) / 1e12  # TFLOP/s of the slower operator
             precisions[pr] = {"forward_ms": round(fm, 3), "transpose_ms": round(am, 3),
-                              "gmacs": round(2.0 * N * K / ((fm + am) * 1e-3) / 1e9, 1)}
+                              "gmacs": round(2.0 * N * K / ((fm + am) * 1e-3) / 1e9, 1),
+                              "tflops_slower_op": round(slow, 1), "peak": PEAK[pr],
+                              "frac": round(slow / PEAK[pr], 4)}
+            if "fp32" in precisions:
+                precisions[pr]["pair_speedup_vs_fp32"] = round(
+                    (precisions["fp32"]["forward_ms"] + precisions["fp32"]["transpose_ms"]) / (fm + am), 2)
             log("pair %s: %.2f + %.2f ms" % (pr, fm, am))
 
     out = {
