@@ -26,7 +26,7 @@ ConvPlan plan_conv_mfma32(const Geom &g, int precision);
 hipError_t launch_conv_mfma32(const Geom &g, int precision, const void *in, const void *H, void *out,
                               const Epi &ep, hipStream_t s);
 bool small_supported(const Geom &g, int dtype, int precision);
-int64_t small_blocks(const Geom &g);
+int64_t small_blocks(const Geom &g, int dtype);
 hipError_t launch_conv_small(const Geom &g, int dtype, const void *in, const void *H, void *out, const Epi &ep,
                              hipStream_t s);
 hipError_t launch_conv_mfma(const ConvPlan &pl, const Geom &g, int dtype, int precision, const void *in,
@@ -94,7 +94,7 @@ ConvPlan plan_conv(const Geom &g, int dtype, int precision) {
   if (use_small(g, dtype, precision)) {
     ConvPlan pl;
     pl.variant = 2;
-    pl.nblocks = small_blocks(g);
+    pl.nblocks = small_blocks(g, dtype);
     pl.grid = dim3((unsigned)pl.nblocks);
     pl.block = dim3(256);
     pl.lds_bytes = 0;

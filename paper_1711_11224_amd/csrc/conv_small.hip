@@ -15,6 +15,10 @@
 //     lands in accumulator z mod kz, a compile-time index.  A plane is
 //     finished (fused epilogue) when its last input plane has been added.
 // Taps live in LDS (rows padded to 8) and are read as uniform float4.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+
 #include "ndc_device.h"
 #include "ndc_internal.h"
 
@@ -28,7 +32,6 @@ constexpr int SRX = 4;           // x outputs per thread
 constexpr int STX = 16 * SRX;    // 64 output columns
 constexpr int STY = ST / 16;     // 16 output rows
 constexpr int SMAXK = 7;         // max taps per axis
-constexpr int SZC = 16;          // output planes per work-group
 constexpr int SCOLS = STX + SMAXK - 1;              // staged columns (70)
 constexpr int SSTRIDE = (SCOLS + 3) / 4 * 4 + 4;    // 76
 constexpr int SROWS = STY + SMAXK - 1;              // 22
@@ -51,7 +54,8 @@ __host__ __device__ constexpr size_t small_lds_bytes(int kz) {
 
 template <typename T, int KX, int KZ>
 __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in, const T *__restrict__ H,
-                                                        T *__restrict__ out, Geom g, Epi ep, int nbx, int nby) {
+                                                        T *__restrict__ out, Geom g, Epi ep, int nbx, int nby,
+                                                        int zc) {
   if (ep.phase && !((1 << *ep.phase) & ep.phase_mask)) return;
   extern __shared__ __align__(16) unsigned char small_lds[];
   T *planes = (T *)small_lds;                  // 2 x SPLANE
@@ -60,7 +64,7 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
 
   const int id = blockIdx.x;
   const int tx = id % nbx, ty = (id / nbx) % nby, tz = id / (nbx * nby);
-  const int x0 = tx * STX, y0 = ty * STY, zlo = tz * SZC, zhi = min(g.oz, zlo + SZC);
+  const int x0 = tx * STX, y0 = ty * STY, zlo = tz * zc, zhi = min(g.oz, zlo + zc);
   const int tid = threadIdx.x, lx = tid % 16, ly = tid / 16;
   const int rows = STY + g.ky - 1, cols = STX + KX - 1;
   double s0 = 0.0, s1 = 0.0;
@@ -229,11 +233,49 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
   }
 }
 
+// Output planes per work-group: about 16, with the number of work-groups
+// snapped to a whole number of rounds of resident work-groups (a partial last
+// round leaves most CUs idle while it runs), and no fewer than 2 (kz - 1),
+// which bounds the restaged z halo to half the planes.
+int small_zchunk(const Geom &g, int per_cu) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1) {
+    (void)hipGetLastError();
+    cus = 1;
+  }
+  const double columns = (double)((g.ox + STX - 1) / STX) * ((g.oy + STY - 1) / STY);
+  const double per_round = (double)per_cu * cus / columns;  // z chunks per column in one round
+  const double rounds = std::max(1.0, std::round(std::ceil(g.oz / 16.0) / per_round));
+  const int64_t chunks = std::max<int64_t>(1, std::llround(rounds * per_round));
+  const int zc = (int)((g.oz + chunks - 1) / chunks);
+  return std::max(zc, std::min(g.oz, std::max(1, 2 * (g.kz - 1))));
+}
+
+// Work-groups of one instantiation that fit on a CU at once (registers and
+// LDS), from the runtime's occupancy calculator, once per process.
+template <typename T, int KX, int KZ>
+int small_occupancy() {
+  static std::atomic<int> n{0};
+  int v = n.load(std::memory_order_relaxed);
+  if (v == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, conv_small_kernel<T, KX, KZ>, ST, small_lds_bytes<T>(KZ)) !=
+            hipSuccess ||
+        v < 1) {
+      (void)hipGetLastError();
+      v = 1;
+    }
+    n.store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
 template <typename T, int KX, int KZ>
 hipError_t launch_small_t(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
-  const int nbx = (g.ox + STX - 1) / STX, nby = (g.oy + STY - 1) / STY, nbz = (g.oz + SZC - 1) / SZC;
+  const int zc = small_zchunk(g, small_occupancy<T, KX, KZ>());
+  const int nbx = (g.ox + STX - 1) / STX, nby = (g.oy + STY - 1) / STY, nbz = (g.oz + zc - 1) / zc;
   hipLaunchKernelGGL((conv_small_kernel<T, KX, KZ>), dim3(nbx * nby * nbz), dim3(ST), small_lds_bytes<T>(KZ), s,
-                     (const T *)in, (const T *)H, (T *)out, g, ep, nbx, nby);
+                     (const T *)in, (const T *)H, (T *)out, g, ep, nbx, nby, zc);
   return hipGetLastError();
 }
 
@@ -259,6 +301,26 @@ hipError_t launch_small_dt(const Geom &g, const void *in, const void *H, void *o
   }
 }
 
+template <typename T, int KZ>
+int small_occupancy_kz(int kx) {
+  switch (kx) {
+    case 1: return small_occupancy<T, 1, KZ>();
+    case 3: return small_occupancy<T, 3, KZ>();
+    case 5: return small_occupancy<T, 5, KZ>();
+    default: return small_occupancy<T, 7, KZ>();
+  }
+}
+
+template <typename T>
+int small_occupancy_dt(const Geom &g) {
+  switch (g.kz) {
+    case 1: return small_occupancy_kz<T, 1>(g.kx);
+    case 3: return small_occupancy_kz<T, 3>(g.kx);
+    case 5: return small_occupancy_kz<T, 5>(g.kx);
+    default: return small_occupancy_kz<T, 7>(g.kx);
+  }
+}
+
 }  // namespace
 
 bool small_supported(const Geom &g, int dtype, int precision) {
@@ -270,8 +332,9 @@ bool small_supported(const Geom &g, int dtype, int precision) {
   return bytes <= 64 * 1024;
 }
 
-int64_t small_blocks(const Geom &g) {
-  return (int64_t)((g.ox + STX - 1) / STX) * ((g.oy + STY - 1) / STY) * ((g.oz + SZC - 1) / SZC);
+int64_t small_blocks(const Geom &g, int dtype) {
+  const int zc = small_zchunk(g, dtype == NDC_F64 ? small_occupancy_dt<double>(g) : small_occupancy_dt<float>(g));
+  return (int64_t)((g.ox + STX - 1) / STX) * ((g.oy + STY - 1) / STY) * ((g.oz + zc - 1) / zc);
 }
 
 hipError_t launch_conv_small(const Geom &g, int dtype, const void *in, const void *H, void *out, const Epi &ep,
