@@ -298,18 +298,20 @@ def bench_small_psf(nd, torch, reps=5):
     return out
 
 
-def cpu_baseline(cfg, target_s=15.0):
+def cpu_baseline(cfg, nd=None, torch=None, target_s=15.0):
     """The FP64 oracle, as it stands, on a bounded random sample of forward
     and transpose outputs of the same workload (each output is a full
-    K-tap sum)."""
+    K-tap sum).  With the library at hand, the same sampled outputs of the
+    GPU operators in each precision are compared with the oracle's (relative
+    L2 error; inputs are FP32 values on both sides)."""
     import oracle
     import synth
     rng = np.random.default_rng(99)
     m, ks = cfg.shape, cfg.psf_shape
     p = [(k - 1) // 2 for k in ks]
-    x = rng.random(m)
-    h = synth.psf_for(cfg)
-    r = rng.standard_normal([a + 2 * b for a, b in zip(m, p)])
+    x = rng.random(m).astype(np.float32).astype(np.float64)
+    h = synth.psf_for(cfg).astype(np.float32).astype(np.float64)
+    r = rng.standard_normal([a + 2 * b for a, b in zip(m, p)]).astype(np.float32).astype(np.float64)
     K = int(np.prod(ks))
     nthreads = oracle.threads()
     # interior forward outputs (every tap in range) and any transpose output
@@ -319,22 +321,39 @@ def cpu_baseline(cfg, target_s=15.0):
     n = 64
     while True:
         t0 = time.time()
-        oracle.conv_full_at(x, h, interior(n))
-        oracle.conv_adjoint_at(r, h, rng.integers(0, int(np.prod(m)), size=n))
+        i_f, i_a = interior(n), rng.integers(0, int(np.prod(m)), size=n)
+        y_f = oracle.conv_full_at(x, h, i_f)
+        g_a = oracle.conv_adjoint_at(r, h, i_a)
         dt = time.time() - t0
         if dt >= target_s or n >= 1 << 22:
             break
         n = int(n * min(8.0, max(2.0, 1.2 * target_s / max(dt, 1e-3))))
     macs = 2.0 * n * K
-    return {"value": macs / dt / 1e9, "unit": "GMAC/s", "cores": nthreads, "kind": "oracle",
-            "sample": "%d forward + %d transpose outputs of the 128x512x512 / 63x31x31 workload, %d taps each, "
-                      "FP64 (%.1f s on %s)" % (n, n, K, dt, cpu_model())}
+    out = {"value": macs / dt / 1e9, "unit": "GMAC/s", "cores": nthreads, "kind": "oracle",
+           "sample": "%d forward + %d transpose outputs of the 128x512x512 / 63x31x31 workload, %d taps each, "
+                     "FP64 (%.1f s on %s)" % (n, n, K, dt, cpu_model())}
+    if nd is not None:
+        def rel(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        xt = torch.from_numpy(x.astype(np.float32)).cuda()
+        ht = torch.from_numpy(h.astype(np.float32)).cuda()
+        rt = torch.from_numpy(r.astype(np.float32)).cuda()
+        tf, ta = torch.from_numpy(i_f).cuda(), torch.from_numpy(i_a).cuda()
+        acc = {}
+        for pr in ("fp32", "bf16", "split_bf16"):
+            yg = nd.conv_full_nd(xt, ht, precision=pr).view(-1)[tf].double().cpu().numpy()
+            gg = nd.conv_adjoint_nd(rt, ht, precision=pr).view(-1)[ta].double().cpu().numpy()
+            acc[pr] = {"forward": float("%.3g" % rel(yg, y_f)), "transpose": float("%.3g" % rel(gg, g_a))}
+        out["accuracy_vs_oracle"] = acc
+        out["accuracy_sample"] = "the same %d forward and %d transpose outputs, relative L2 error" % (n, n)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="timed iterations, in one call (the metric workload runs 100)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "split_bf16"])
     ap.add_argument("--pair-reps", type=int, default=5)
@@ -449,7 +468,7 @@ def main():
         out["batched"] = bench_batched(nd, torch, table=args.tuning_table)
         log("batched:", out["batched"])
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+        out["cpu_baseline"] = cpu_baseline(cfg, nd, torch)
     print(json.dumps(out), flush=True)
 
 
