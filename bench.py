@@ -25,6 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32": 157.3, "bf16": 2500.0, "split_bf16": 2500.0 / 3.0, "hbm": 8000.0}
+# the files the FP32 matrix-core tile is compiled from (its HBM counters stay
+# valid while these are unchanged)
+TILE_SOURCES = ["paper_1711_11224_amd/csrc/conv_mfma.hip", "paper_1711_11224_amd/csrc/mfma_tile.h",
+                "paper_1711_11224_amd/csrc/ndc_device.h", "paper_1711_11224_amd/csrc/ndc_internal.h",
+                "include/ndconv.h"]
 
 
 def log(*a):
@@ -80,10 +85,10 @@ def time_pairs(nd, torch, x, h, precision, reps):
 def measured_traffic(kernel_key, forward=True):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     passes (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known
-    size), or None when the kernel sources changed since they were taken.
+    size), or None when the kernel's sources (TILE_SOURCES) changed since
+    they were taken.
     Both operators may run the same kernel instantiation; the forward launch
     is the one with the larger grid (its output extent m+2p exceeds m)."""
-    import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_conv_128x512x512_psf63x31x31.json")
     try:
@@ -91,8 +96,8 @@ def measured_traffic(kernel_key, forward=True):
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1711_11224_amd", "csrc", "*"))):
-        h.update(open(p, "rb").read())
+    for p in TILE_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
     k = sorted((int(key.split("/")[1]), v) for key, v in rec.get("kernels", {}).items()
                if key.split("/")[0] == kernel_key)
     if rec.get("csrc_sha256") != h.hexdigest() or not k or len(k) > 2:
