@@ -97,10 +97,10 @@ def test_reduced_precision(nd, m, p, prec):
 # 3 and 4 Toeplitz chunks per row (kx 11, 17 / 19, 31, 33), 2, 3 and 4 x blocks
 # per wave with ragged x tails, several 64-row tiles, ky = 33, 2p >= m, z groups
 # with ragged tails, a 2-D problem (three of the four planes of a group idle),
-# and a 256^3 volume with >= 512 work-groups (the widest tiles).
+# a 256^3 volume with >= 512 work-groups (the widest tiles), and 1-D.
 WIDE_CASES = [((9, 70, 130), (2, 16, 15)), ((5, 100, 64), (1, 5, 5)), ((3, 40, 250), (4, 3, 8)),
               ((4, 30, 90), (2, 4, 9)), ((80, 150), (12, 16)), ((2, 10, 20), (1, 8, 12)),
-              ((6, 20, 256), (2, 2, 10)), ((256, 256, 256), (0, 1, 5))]
+              ((6, 20, 256), (2, 2, 10)), ((256, 256, 256), (0, 1, 5)), ((300,), (12,))]
 
 
 @pytest.mark.parametrize("form", ["1", "0"], ids=["mfma32x32", "mfma4x4"])
@@ -124,15 +124,17 @@ def test_reduced_precision_wide_rows(nd, m, p, prec, form, monkeypatch):
     assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[prec]
 
 
+@pytest.mark.parametrize("rule,mu", [("fixed", 0.0), ("cauchy", 0.0), ("bb", 0.0), ("fixed", 0.05)])
 @pytest.mark.parametrize("prec,tol", [("bf16", 5e-2), ("split_bf16", 5e-4)])
-def test_deconv_reduced_precision_wide_rows(nd, prec, tol, monkeypatch):
-    """Five projected-gradient steps with the 32x32x16 operators (every
-    epilogue: residual, update, objective partial sums) against the FP64
-    oracle.  Each step moves X by delta*G with G from both operators, so the
-    iterate and f carry a few times the operators' relative error e; the
-    bound is 5e for each precision, as for f(X^0) at the metric size."""
+def test_deconv_reduced_precision_wide_rows(nd, prec, tol, rule, mu, monkeypatch):
+    """Five projected-gradient steps with the 32x32x16 operators against the
+    FP64 oracle, for each first-trial rule and with the Laplacian term: the
+    residual, update, gradient and norm epilogues all run on this tile.
+    Each step moves X by delta*G with G from both operators, so the iterate
+    and f carry a few times the operators' relative error e; the bound is 5e
+    for each precision, as for f(X^0) at the metric size."""
     monkeypatch.setenv("NDC_MFMA32", "1")
-    say("case deconv wide %s" % prec)
+    say("case deconv wide %s %s mu=%g" % (prec, rule, mu))
     rng = np.random.default_rng(21)
     m, p = (6, 40, 70), (2, 6, 12)
     h = rng.random([2 * q + 1 for q in p]).astype(np.float32) + 0.1
@@ -141,10 +143,10 @@ def test_deconv_reduced_precision_wide_rows(nd, prec, tol, monkeypatch):
     y = (oracle.conv_full(xt, h) + 0.01 * rng.standard_normal([a + 2 * b for a, b in zip(m, p)])).astype(np.float32)
     x0 = np.full(m, float(xt.mean()), dtype=np.float32)
     xg, st, info = nd.deconv_iterate(gpu(y, np.float32), gpu(h, np.float32), gpu(x0, np.float32), 5, lam=0.01,
-                                     precision=prec)
+                                     precision=prec, rule=rule, mu=mu)
     torch.cuda.synchronize()
     xo, so, done, status = oracle.deconv(y.astype(np.float64), h.astype(np.float64), x0.astype(np.float64), 5,
-                                         lam=0.01)
+                                         lam=0.01, rule=rule, mu=mu)
     assert info.cpu().tolist() == [5, 0] and (done, status) == (5, 0)
     f = st.cpu().numpy()[:, 0]
     assert np.all(np.diff(f) < 0)
