@@ -80,6 +80,13 @@ NDC_API int conv_full_nd(int n, const int64_t *m, const int64_t *p, const void *
 NDC_API int conv_adjoint_nd(int n, const int64_t *m, const int64_t *p, const void *R, const void *H,
                     void *X, int dtype, int precision, void *stream);
 
+/* Non-finite inputs (both operators): the matrix-core kernels also multiply
+ * the zeros of their Toeplitz operands, so an Inf or NaN input element can
+ * turn outputs near it into NaN even where no tap reaches it: up to 3
+ * columns away in FP32 and in the narrow-row bf16 forms, up to 31 columns in
+ * the bf16 forms for rows of 11-33 taps, and up to 3 planes away in FP32.
+ * Finite inputs are unaffected (0 * x = 0). */
+
 /* Gradient of 1/2 ||X (x) H - Y||^2 with respect to H, given the residual
  * G = X (x) H - Y (extent m_i+2p_i):  dH[j] = sum_k X[k] G[k+j],
  * j in prod [0,2p_i].  Convolution commutes, so this is Property 1's
