@@ -78,8 +78,10 @@ def test_conv_full_and_adjoint(nd, m, p, dtype):
     assert rel_l2(g, go) <= TOL[dtype]
 
 
+# the last two exceed the matrix-core tiles (ky = 37, kx = 41): general kernel
 @pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
-@pytest.mark.parametrize("m,p", [((5, 37, 70), (2, 3, 4)), ((6, 40, 100), (3, 7, 15)), ((33, 47), (4, 6))])
+@pytest.mark.parametrize("m,p", [((5, 37, 70), (2, 3, 4)), ((6, 40, 100), (3, 7, 15)), ((33, 47), (4, 6)),
+                                 ((3, 80, 60), (1, 18, 4)), ((3, 20, 100), (1, 2, 20))])
 def test_reduced_precision(nd, m, p, prec):
     say("case prec m=%s p=%s %s" % (m, p, prec))
     rng = np.random.default_rng(11)
