@@ -29,8 +29,8 @@
  *   - ora_conv_full_at / ora_conv_adjoint_at : the same two sums evaluated
  *                                only at a list of flat output indices.
  *
- * Arrays are C order (axis 0 slowest), the "partitioning along rows" of the
- * vectorisation {.}^v under Eq. 1.  Sums run in the natural lexicographic
+ * Arrays are C order (axis 0 slowest): the row-by-row stacking that the
+ * vectorisation {.}^v under Eq. 1 uses.  Sums run in the natural lexicographic
  * tap order; there is no blocking, fusion or reordering.  OpenMP splits the
  * output elements statically; each element is summed by one thread in the
  * same order, so results do not depend on the thread count.
