@@ -8,7 +8,7 @@ import pytest
 
 from tests.conftest import ROOT
 
-nd = pytest.importorskip("paper_1711_11224_amd._native")
+nd = pytest.importorskip("paper_1711_11224_amd._native", exc_type=ImportError)
 lib = nd.lib
 I = nd.i64_array
 F32, F64 = nd.NDC_F32, nd.NDC_F64
