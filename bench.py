@@ -142,10 +142,13 @@ def bench_differentiable(nd, torch, reps=3):
     e1.record(s)
     torch.cuda.synchronize()
     dh_ms = e0.elapsed_time(e1) / reps
+    # the plain FP32 operators on the same tensors (forward + transpose, no autograd)
+    fwd_ms, adj_ms = time_pairs(nd, torch, x.detach(), h.detach(), "fp32", reps)
     del y
     return {"workload": "X 64x256x256, PSF 41x21x21, FP32", "forward_backward_ms": round(ms, 3),
             "gmacs": round(3.0 * N * K / (ms * 1e-3) / 1e9, 1), "dH_ms": round(dh_ms, 3),
-            "dH_gmacs": round(N * K / (dh_ms * 1e-3) / 1e9, 1)}
+            "dH_gmacs": round(N * K / (dh_ms * 1e-3) / 1e9, 1),
+            "plain_forward_plus_transpose_ms": round(fwd_ms + adj_ms, 3)}
 
 
 def bench_batched(nd, torch, steps=5, table=None):
@@ -180,11 +183,38 @@ def bench_batched(nd, torch, steps=5, table=None):
     done = int(info[:, 0].min())
     pair_ms = time_plan_pair(plan, torch, xs, hs)
     plan.close()
+    # the plain FP32 path on the same volumes: one single-volume call per volume
+    x1 = [x.clone() for x in xs]
+    for v in range(len(cfgs)):  # warm-up (plans, workspaces)
+        nd.deconv_iterate(ys[v], hs[v], x1[v], 1)
+    torch.cuda.synchronize()
+    x1 = [x.clone() for x in xs]
+    e0.record(s)
+    for v in range(len(cfgs)):
+        nd.deconv_iterate(ys[v], hs[v], x1[v], steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1)
+    y1 = [nd.conv_full_nd(xs[v], hs[v]) for v in range(len(cfgs))]
+    g1 = [nd.conv_adjoint_nd(y1[v], hs[v]) for v in range(len(cfgs))]
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(3):
+        for v in range(len(cfgs)):
+            nd.conv_full_nd(xs[v], hs[v], Y=y1[v])
+            nd.conv_adjoint_nd(y1[v], hs[v], X=g1[v])
+    e1.record(s)
+    torch.cuda.synchronize()
+    seq_pair_ms = e0.elapsed_time(e1) / 3
     return {"workload": "64 volumes 32^3..96x160x160, PSFs 9..31 per axis, FP32", "tuning": list(plan.tuning),
             "tune_or_lookup_s": round(tune_s, 2), "steps": steps, "steps_accepted_min": done,
             "ms_per_step": round(ms / steps, 3), "iters_per_s": round(steps / (ms * 1e-3), 2),
             "gmacs": round(macs * done / (ms * 1e-3) / 1e9, 1),
-            "conv_pair_ms": round(pair_ms, 3), "conv_pair_gmacs": round(macs / (pair_ms * 1e-3) / 1e9, 1)}
+            "conv_pair_ms": round(pair_ms, 3), "conv_pair_gmacs": round(macs / (pair_ms * 1e-3) / 1e9, 1),
+            "single_volume_calls": {"ms_per_step": round(seq_ms / steps, 3),
+                                    "conv_pair_ms": round(seq_pair_ms, 3),
+                                    "step_speedup_of_batched": round(seq_ms / ms, 2),
+                                    "pair_speedup_of_batched": round(seq_pair_ms / pair_ms, 2)}}
 
 
 def time_plan_pair(plan, torch, xs, hs, reps=3):
