@@ -369,3 +369,38 @@ def test_deconv_resume_is_exact(nd):
     xb, _, _ = nd.deconv_iterate(y, hg, torch.full(m, 0.3, device="cuda"), 3)
     xb, _, _ = nd.deconv_iterate(y, hg, xb, 3)
     assert torch.equal(xa, xb)
+
+
+def _random_wide_cases(n, seed=31):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nd_ = int(rng.integers(1, 4))
+        px = int(rng.integers(5, 17))  # kx 11..33
+        p = [int(rng.integers(0, 6)) for _ in range(nd_ - 1)] + [px]
+        if nd_ >= 2:
+            p[-2] = int(rng.integers(0, 17))  # ky up to 33
+        m = [int(rng.integers(1, 12)) for _ in range(nd_ - 2)] + ([int(rng.integers(1, 90))] if nd_ >= 2 else []) + \
+            [int(rng.integers(1, 200))]
+        out.append((tuple(m), tuple(p)))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
+@pytest.mark.parametrize("m,p", _random_wide_cases(12))
+def test_reduced_precision_wide_rows_random(nd, m, p, prec, monkeypatch):
+    """Seeded random shapes (1-D to 3-D, 2p >= m included) on the forced
+    32x32x16 form against the oracle."""
+    monkeypatch.setenv("NDC_MFMA32", "1")
+    say("case wide random m=%s p=%s %s" % (m, p, prec))
+    rng = np.random.default_rng(hash((m, p)) % 2**32)
+    h = rng.standard_normal([2 * q + 1 for q in p]).astype(np.float32)
+    x = rng.random(m).astype(np.float32)
+    y = nd.conv_full_nd(gpu(x, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
+    yo = oracle.conv_full(x, h)
+    assert y.shape == yo.shape
+    assert rel_l2(y, yo) <= TOL[prec]
+    r = rng.standard_normal(yo.shape).astype(np.float32)
+    g = nd.conv_adjoint_nd(gpu(r, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
+    assert g.shape == tuple(m)
+    assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[prec]
