@@ -404,3 +404,34 @@ def test_reduced_precision_wide_rows_random(nd, m, p, prec, monkeypatch):
     g = nd.conv_adjoint_nd(gpu(r, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
     assert g.shape == tuple(m)
     assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[prec]
+
+
+def _random_cases(n, seed=57):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        nd_ = int(rng.integers(1, 4))
+        # half axis widths from 0 to 20: small-PSF kernel, matrix-core tile and, past 16, the general kernel
+        p = tuple(int(rng.integers(0, 4)) if rng.random() < 0.4 else int(rng.integers(0, 21)) for _ in range(nd_))
+        m = tuple(int(rng.integers(1, 9 if i < nd_ - 2 else 70)) for i in range(nd_))
+        out.append((m, p))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("m,p", _random_cases(12))
+def test_conv_random_shapes(nd, m, p, dtype):
+    """Seeded random shapes across all kernels (1-D to 3-D, 2p >= m included)."""
+    say("case random m=%s p=%s %s" % (m, p, dtype))
+    rng = np.random.default_rng(hash((m, p, dtype)) % 2**32)
+    npdt = np.float32 if dtype == "fp32" else np.float64
+    h = rng.standard_normal([2 * q + 1 for q in p]).astype(npdt)
+    x = rng.random(m).astype(npdt)
+    y = nd.conv_full_nd(gpu(x, npdt), gpu(h, npdt)).cpu().numpy()
+    yo = oracle.conv_full(x, h)
+    assert y.shape == yo.shape
+    assert rel_l2(y, yo) <= TOL[dtype]
+    r = rng.standard_normal(yo.shape).astype(npdt)
+    g = nd.conv_adjoint_nd(gpu(r, npdt), gpu(h, npdt)).cpu().numpy()
+    assert g.shape == tuple(m)
+    assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[dtype]
