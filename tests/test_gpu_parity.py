@@ -435,3 +435,18 @@ def test_conv_random_shapes(nd, m, p, dtype):
     g = nd.conv_adjoint_nd(gpu(r, npdt), gpu(h, npdt)).cpu().numpy()
     assert g.shape == tuple(m)
     assert rel_l2(g, oracle.conv_adjoint(r, h)) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp64"])
+@pytest.mark.parametrize("m,p", _random_cases(10, seed=91))
+def test_conv_dH_random_shapes(nd, m, p, dtype):
+    """PSF gradient on seeded random shapes (1-D to 3-D)."""
+    say("case dH random m=%s p=%s %s" % (m, p, dtype))
+    rng = np.random.default_rng(hash((m, p, dtype, 1)) % 2**32)
+    npdt = np.float32 if dtype == "fp32" else np.float64
+    x = rng.random(m).astype(npdt)
+    gr = rng.standard_normal([a + 2 * b for a, b in zip(m, p)]).astype(npdt)
+    ps = [2 * q + 1 for q in p]
+    dh = nd.conv_dH_nd(gpu(x, npdt), gpu(gr, npdt), ps).cpu().numpy()
+    assert dh.shape == tuple(ps)
+    assert rel_l2(dh, oracle.conv_dH(x, gr, ps)) <= TOL[dtype]
