@@ -207,3 +207,27 @@ def test_autotuner_table(nd, tmp_path):
     plan = nd.batched.plan_for(shapes, psfs, table=table)
     assert plan.tuning == best
     plan.close()
+
+
+@pytest.mark.parametrize("tuning", [(4, 2, 2, 1), (2, 1, 0, 0)])
+def test_batch_conv_random_volumes_vs_oracle(nd, tuning):
+    """A seeded batch of 10 random volumes (extents 1..40 per axis, 2p >= m
+    included) with their own PSFs (kx 3..33, ky <= 33) against the oracle."""
+    say("case batch random", tuning)
+    rng = np.random.default_rng(77)
+    shapes, psfs = [], []
+    for _ in range(10):
+        shapes.append(tuple(int(rng.integers(1, 41)) for _ in range(3)))
+        psfs.append((2 * int(rng.integers(0, 9)) + 1, 2 * int(rng.integers(0, 17)) + 1,
+                     2 * int(rng.integers(1, 17)) + 1))
+    xs = [rng.random(m).astype(np.float32) for m in shapes]
+    hs = [rng.standard_normal(k).astype(np.float32) for k in psfs]
+    plan = nd.batched.BatchPlan(shapes, psfs, tuning=tuning)
+    gh = [torch.from_numpy(h).cuda() for h in hs]
+    ys = plan.conv_full([torch.from_numpy(x).cuda() for x in xs], gh)
+    rs = [np.random.default_rng(i).standard_normal(tuple(y.shape)).astype(np.float32) for i, y in enumerate(ys)]
+    gs = plan.conv_adjoint([torch.from_numpy(r).cuda() for r in rs], gh)
+    for v, (x, h) in enumerate(zip(xs, hs)):
+        assert rel_l2(ys[v].cpu().numpy(), oracle.conv_full(x, h)) <= 1e-5
+        assert rel_l2(gs[v].cpu().numpy(), oracle.conv_adjoint(rs[v], h)) <= 1e-5
+    plan.close()
