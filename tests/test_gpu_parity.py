@@ -450,3 +450,31 @@ def test_conv_dH_random_shapes(nd, m, p, dtype):
     dh = nd.conv_dH_nd(gpu(x, npdt), gpu(gr, npdt), ps).cpu().numpy()
     assert dh.shape == tuple(ps)
     assert rel_l2(dh, oracle.conv_dH(x, gr, ps)) <= TOL[dtype]
+
+
+def _random_deconv_cases(n, seed=123):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        nd_ = int(rng.integers(1, 4))
+        m = tuple(int(rng.integers(2, 8 if j < nd_ - 2 else 40)) for j in range(nd_))
+        p = tuple(int(rng.integers(0, 6)) for _ in range(nd_))
+        rule = ("fixed", "cauchy", "bb")[i % 3]
+        lam = float(rng.choice([0.0, 0.05]))
+        mu = float(rng.choice([0.0, 0.02]))
+        out.append((m, p, rule, lam, mu))
+    return out
+
+
+@pytest.mark.parametrize("m,p,rule,lam,mu", _random_deconv_cases(9))
+def test_deconv_random_fp64(nd, m, p, rule, lam, mu):
+    """FP64 deconvolution on seeded random problems (1-D to 3-D, every first
+    trial, with and without the Tikhonov and Laplacian terms): the same
+    decisions as the oracle, X, f and delta to rounding."""
+    say("case deconv random m=%s p=%s %s lam=%g mu=%g" % (m, p, rule, lam, mu))
+    rng = np.random.default_rng(hash((m, p, rule)) % 2**32)
+    h = rng.random([2 * q + 1 for q in p]) + 0.05
+    h /= h.sum()
+    y = oracle.conv_full(rng.random(m) + 0.1, h) + 0.01 * rng.standard_normal([a + 2 * b for a, b in zip(m, p)])
+    x0 = np.full(m, float(np.mean(y)))
+    _check_deconv(nd, y, h, x0, 10, lam, np.float64, 1e-9, 1e-11, rule=rule, tol_d=1e-9, mu=mu)
