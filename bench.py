@@ -401,7 +401,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path here is single-GPU (no collectives); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+              "sharding over several GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
