@@ -10,7 +10,11 @@ the fused residual/objective epilogue, the device-side acceptance decision
 and the commit.  Algorithmic work per step: 2 N K multiply-adds (N = 33.5M
 voxels, K = 60543 taps), zero-padding products not counted.
 
-Prints one JSON line (see the design doc for the field definitions).
+Prints one JSON line: the metric and value (multiply-adds per second of whole
+steps), the roofline of the dominant kernel (its launch time, TFLOP/s against
+the FP32 matrix peak and its HBM bytes from rocprofv3 counters), each precision
+form, the CPU oracle's rate on a bounded sample with each form's error on it,
+and the other workloads (step rules, 2-D, small PSFs, differentiable, batched).
 """
 import argparse
 import json
