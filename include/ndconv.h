@@ -51,7 +51,7 @@ extern "C" {
 typedef enum {
   NDC_OK = 0,
   NDC_EINVAL = -1,       /* bad n, extent, half-width, count, pointer or scalar */
-  NDC_EUNSUPPORTED = -2, /* valid request this build does not implement      */
+  NDC_EUNSUPPORTED = -2, /* valid request the library does not implement     */
   NDC_EALIAS = -3,       /* an output overlaps an input or another output     */
   NDC_ENONFINITE = -4,   /* reported in deconvolution status words only       */
   NDC_EDEVICE = -5,      /* a HIP runtime call or kernel launch failed         */

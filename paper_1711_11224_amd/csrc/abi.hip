@@ -197,7 +197,7 @@ const char *ndc_strerror(int status) {
   switch (status) {
     case NDC_OK: return "success";
     case NDC_EINVAL: return "invalid argument (rank, extent, half-width, count, pointer or scalar)";
-    case NDC_EUNSUPPORTED: return "valid request not supported by this build (rank > 3, sizes, or bf16 with FP64)";
+    case NDC_EUNSUPPORTED: return "valid request the library does not support (rank > 3, sizes, or bf16 with FP64)";
     case NDC_EALIAS: return "an output buffer overlaps an input or another output";
     case NDC_ENONFINITE: return "non-finite objective";
     case NDC_EDEVICE: return "HIP runtime or kernel launch failure";
