@@ -14,8 +14,8 @@ by Gaussian PSFs, with photon and read noise).
 """
 from .volumes import (CONFIGS, PAPER_2D, SWEEP_PSFS, VolumeConfig, add_noise, batched_configs, crossing_lines,
                       flat_start, gaussian_factors, gaussian_noise, gaussian_psf, make_objects, piecewise_image,
-                      psf_for)
+                      psf_for, stable_seed)
 
 __all__ = ["CONFIGS", "PAPER_2D", "SWEEP_PSFS", "VolumeConfig", "add_noise", "batched_configs", "crossing_lines",
            "flat_start", "gaussian_factors", "gaussian_noise", "gaussian_psf", "make_objects", "piecewise_image",
-           "psf_for"]
+           "psf_for", "stable_seed"]

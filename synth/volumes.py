@@ -2,7 +2,15 @@
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence, Tuple
 
+import zlib
+
 import numpy as np
+
+
+def stable_seed(*parts) -> int:
+    """A 32-bit seed from the repr of `parts` (CRC-32): the same on every run
+    and in every process, unlike hash(), which randomises strings."""
+    return zlib.crc32(repr(parts).encode())
 
 
 @dataclass(frozen=True)

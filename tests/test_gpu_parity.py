@@ -63,7 +63,7 @@ CASES = [
 @pytest.mark.parametrize("m,p", CASES)
 def test_conv_full_and_adjoint(nd, m, p, dtype):
     say("case conv m=%s p=%s %s" % (m, p, dtype))
-    rng = np.random.default_rng(hash((m, p)) % 2**32)
+    rng = np.random.default_rng(synth.stable_seed(m, p))
     npdt = np.float32 if dtype == "fp32" else np.float64
     h = rng.standard_normal([2 * q + 1 for q in p]).astype(npdt)  # asymmetric, signed
     x = rng.random(m).astype(npdt)
@@ -113,7 +113,7 @@ def test_reduced_precision_wide_rows(nd, m, p, prec, form, monkeypatch):
     library picks one by volume; NDC_MFMA32 forces it here)."""
     monkeypatch.setenv("NDC_MFMA32", form)
     say("case wide m=%s p=%s %s form %s" % (m, p, prec, form))
-    rng = np.random.default_rng(hash((m, p)) % 2**32)
+    rng = np.random.default_rng(synth.stable_seed(m, p))
     h = rng.standard_normal([2 * q + 1 for q in p]).astype(np.float32)  # asymmetric, signed
     x = rng.random(m).astype(np.float32)
     y = nd.conv_full_nd(gpu(x, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
@@ -393,7 +393,7 @@ def test_reduced_precision_wide_rows_random(nd, m, p, prec, monkeypatch):
     32x32x16 form against the oracle."""
     monkeypatch.setenv("NDC_MFMA32", "1")
     say("case wide random m=%s p=%s %s" % (m, p, prec))
-    rng = np.random.default_rng(hash((m, p)) % 2**32)
+    rng = np.random.default_rng(synth.stable_seed(m, p))
     h = rng.standard_normal([2 * q + 1 for q in p]).astype(np.float32)
     x = rng.random(m).astype(np.float32)
     y = nd.conv_full_nd(gpu(x, np.float32), gpu(h, np.float32), precision=prec).cpu().numpy()
@@ -423,7 +423,7 @@ def _random_cases(n, seed=57):
 def test_conv_random_shapes(nd, m, p, dtype):
     """Seeded random shapes across all kernels (1-D to 3-D, 2p >= m included)."""
     say("case random m=%s p=%s %s" % (m, p, dtype))
-    rng = np.random.default_rng(hash((m, p, dtype)) % 2**32)
+    rng = np.random.default_rng(synth.stable_seed(m, p, dtype))
     npdt = np.float32 if dtype == "fp32" else np.float64
     h = rng.standard_normal([2 * q + 1 for q in p]).astype(npdt)
     x = rng.random(m).astype(npdt)
@@ -442,7 +442,7 @@ def test_conv_random_shapes(nd, m, p, dtype):
 def test_conv_dH_random_shapes(nd, m, p, dtype):
     """PSF gradient on seeded random shapes (1-D to 3-D)."""
     say("case dH random m=%s p=%s %s" % (m, p, dtype))
-    rng = np.random.default_rng(hash((m, p, dtype, 1)) % 2**32)
+    rng = np.random.default_rng(synth.stable_seed(m, p, dtype, 1))
     npdt = np.float32 if dtype == "fp32" else np.float64
     x = rng.random(m).astype(npdt)
     gr = rng.standard_normal([a + 2 * b for a, b in zip(m, p)]).astype(npdt)
@@ -472,7 +472,7 @@ def test_deconv_random_fp64(nd, m, p, rule, lam, mu):
     trial, with and without the Tikhonov and Laplacian terms): the same
     decisions as the oracle, X, f and delta to rounding."""
     say("case deconv random m=%s p=%s %s lam=%g mu=%g" % (m, p, rule, lam, mu))
-    rng = np.random.default_rng(hash((m, p, rule)) % 2**32)
+    rng = np.random.default_rng(synth.stable_seed(m, p, rule))
     h = rng.random([2 * q + 1 for q in p]) + 0.05
     h /= h.sum()
     y = oracle.conv_full(rng.random(m) + 0.1, h) + 0.01 * rng.standard_normal([a + 2 * b for a, b in zip(m, p)])

@@ -324,24 +324,44 @@ def _grad(x, y, h, lam):
     return oracle.conv_adjoint(oracle.conv_full(x, h) - y, h) + lam * x
 
 
-@pytest.mark.parametrize("lam", [0.0, 0.3])
-def test_cauchy_trial_minimises_along_the_gradient(lam):
+@pytest.mark.parametrize("lam,mu", [(0.0, 0.0), (0.3, 0.0), (0.0, 0.4), (0.3, 0.05)])
+def test_cauchy_trial_minimises_along_the_gradient(lam, mu):
     """Away from the bound the Cauchy trial is the exact minimiser of
     f(X - t g) over t: the directional derivative vanishes there and nearby
-    t give larger f."""
+    t give larger f.  With mu > 0 the objective and gradient carry the
+    Laplacian term, so the minimiser needs its mu ||L g||^2 in the
+    denominator."""
     rng = np.random.default_rng(21)
     h = rng.random((3, 5, 3))
     y = oracle.conv_full(50.0 + rng.random((4, 9, 7)), h)
     x = 50.0 + rng.random((4, 9, 7))          # far above 0: no clipping
-    g = _grad(x, y, h, lam)
-    d = oracle.first_trial("cauchy", g, h, lam, oracle.initial_delta(h, lam))
+    g = oracle.gradient(x, y, h, lam, mu)
+    d = oracle.first_trial("cauchy", g, h, lam, oracle.initial_delta(h, lam, mu), mu=mu)
     xt = x - d * g
     assert xt.min() > 0
-    slope = float(np.sum(g * _grad(xt, y, h, lam)))
+    slope = float(np.sum(g * oracle.gradient(xt, y, h, lam, mu)))
     assert abs(slope) <= 1e-10 * float(np.sum(g * g))
-    f = oracle.objective(xt, y, h, lam)
-    for t in (0.5, 0.9, 1.1, 2.0):
-        assert oracle.objective(x - t * d * g, y, h, lam) > f
+    f = oracle.objective(xt, y, h, lam, mu)
+    for t in (0.5, 0.9, 0.99, 1.01, 1.1, 2.0):
+        assert oracle.objective(x - t * d * g, y, h, lam, mu) > f
+
+
+@pytest.mark.parametrize("lam,mu", [(0.0, 0.0), (0.2, 0.0), (0.0, 0.3), (0.2, 0.3)])
+def test_cauchy_trial_is_the_dense_rayleigh_quotient(lam, mu):
+    """The Cauchy trial equals <g,g> / g^T (A^T A + lam I + mu L^T L) g with
+    A and L built as dense matrices by the block recursion of Property 1
+    (explicit_A), so no convolution routine enters the reference value."""
+    rng = np.random.default_rng(25)
+    m = (3, 4, 5)
+    h = rng.random((3, 3, 5))
+    g = rng.standard_normal(m)
+    A = oracle.explicit_A(m, h)
+    L = oracle.explicit_A(m, oracle.laplacian(3))
+    gv = g.ravel()
+    hess = A.T @ A + lam * np.eye(gv.size) + mu * L.T @ L
+    ref = float(gv @ gv) / float(gv @ hess @ gv)
+    d = oracle.first_trial("cauchy", g, h, lam, oracle.initial_delta(h, lam, mu), mu=mu)
+    assert abs(d - ref) <= 1e-12 * ref
 
 
 @pytest.mark.parametrize("lam", [0.0, 0.3])
