@@ -155,6 +155,54 @@ def bench_differentiable(nd, torch, reps=3):
             "plain_forward_plus_transpose_ms": round(fwd_ms + adj_ms, 3)}
 
 
+def bench_joint_refinement(nd, torch, steps=20, sigma_steps=60):
+    """Differentiable workload end to end: Y = X (x) H(6, 2.5, 2.5) plus
+    noise (the library's forward), then `steps` joint X / sigma steps from
+    the flat start and the guess (5, 2, 2) (JointRefiner: one forward, the
+    dX / dH backward, a projected X step and an Adam step on log sigma), and
+    `sigma_steps` sigma-only steps with X known, where sigma is identifiable."""
+    import synth
+    from paper_1711_11224_amd.autograd import GaussianPSF, JointRefiner, conv_full_ad
+    cfg = synth.CONFIGS["c5_diff"]
+    xt = torch.tensor(synth.make_objects(cfg), dtype=torch.float32, device="cuda")
+    h = torch.tensor(synth.psf_for(cfg), dtype=torch.float32, device="cuda")
+    b = nd.conv_full_nd(xt, h).cpu().numpy()
+    y = torch.from_numpy(synth.add_noise(b, cfg).astype(np.float32)).cuda()
+    xt = xt * float(cfg.peak_photons / b.max())  # the object in Y's photon units
+    guess = tuple(cfg.extra["guess_sigmas"])
+    x0 = torch.from_numpy(synth.flat_start(y.cpu().numpy(), synth.psf_for(cfg), cfg.shape).astype(np.float32)).cuda()
+    model = GaussianPSF(cfg.psf_shape, guess)
+    ref = JointRefiner(y, x0, model, lr=0.02)
+    first = float(ref.step())  # warm-up
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        last = ref.step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    joint_ms = e0.elapsed_time(e1) / steps
+    sig_joint = [round(float(v), 3) for v in model.sigmas().detach().cpu()]
+    m2 = GaussianPSF(cfg.psf_shape, guess)
+    opt = torch.optim.Adam(m2.parameters(), lr=0.03)
+    for _ in range(sigma_steps):
+        opt.zero_grad()
+        loss = 0.5 * ((conv_full_ad(xt, m2()) - y) ** 2).sum()
+        loss.backward()
+        opt.step()
+    sig_known = m2.sigmas().detach().cpu().numpy()
+    true = np.array(cfg.sigmas)
+    err0 = float(np.abs(np.array(guess) - true).max())
+    N, K = int(np.prod(cfg.shape)), int(np.prod(cfg.psf_shape))
+    return {"joint_steps": steps, "joint_ms_per_step": round(joint_ms, 3),
+            "joint_gmacs": round(3.0 * N * K / (joint_ms * 1e-3) / 1e9, 1),
+            "joint_loss_first_last": [first, float(last)], "joint_sigmas": sig_joint,
+            "known_x_sigma_steps": sigma_steps, "known_x_sigmas": [round(float(v), 3) for v in sig_known],
+            "known_x_sigma_error_first_last": [round(err0, 3), round(float(np.abs(sig_known - true).max()), 4)],
+            "true_sigmas": list(cfg.sigmas), "guess_sigmas": list(guess)}
+
+
 def bench_batched(nd, torch, steps=5, table=None):
     """Batched workload: 64 volumes of 32^3 .. 96x160x160, each with its own
     Gaussian PSF of odd extents 9..31, FP32, one hipGraph-captured step per
@@ -234,6 +282,31 @@ def time_plan_pair(plan, torch, xs, hs, reps=3):
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def deconv_rate(nd, torch, y, h, x0, precision, steps):
+    """Deconvolution iterations per second in one precision form: one call of
+    `steps` iterations from X^0 (after a 1-step warm-up call), HIP events on
+    the launching stream; the objective reached is reported beside it."""
+    if steps <= 0:
+        return {}
+    nbytes = nd.deconv_workspace_bytes(list(x0.shape), list(h.shape), torch.float32, precision)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=x0.device)
+    nd.deconv_iterate(y, h, x0.clone(), 1, precision=precision, ws=ws)
+    x = x0.clone()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    _, st, info = nd.deconv_iterate(y, h, x, steps, precision=precision, ws=ws)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    done = int(info.cpu()[0])
+    f = st.cpu().numpy()[: done + 1, 0]
+    del ws
+    return {"deconv_steps": done, "iters_per_s": round(done / (ms * 1e-3), 3),
+            "ms_per_iter": round(ms / max(done, 1), 3), "f_after_steps": float(f[-1])}
 
 
 def bench_step_rules(nd, torch, y, h, x0, ws, steps=10, fixed_max=60):
@@ -332,7 +405,10 @@ def bench_small_psf(nd, torch, reps=5):
         out["%d^3" % k] = {"forward_ms": round(fwd, 4), "transpose_ms": round(adj, 4),
                            "forward_GBps": round(by / (fwd * 1e-3) / 1e9, 1),
                            "transpose_GBps": round(by / (adj * 1e-3) / 1e9, 1),
-                           "hbm_frac": round(by / (min(fwd, adj) * 1e-3) / 8e12, 3),
+                           "forward_hbm_frac": round(by / (fwd * 1e-3) / 8e12, 3),
+                           "transpose_hbm_frac": round(by / (adj * 1e-3) / 8e12, 3),
+                           # the slower operator bounds a step, as in the main roofline
+                           "hbm_frac": round(by / (max(fwd, adj) * 1e-3) / 8e12, 3),
                            "gmacs": round(2.0 * N * k ** 3 / ((fwd + adj) * 1e-3) / 1e9, 1)}
     return out
 
@@ -396,6 +472,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "split_bf16"])
     ap.add_argument("--pair-reps", type=int, default=5)
+    ap.add_argument("--precision-steps", type=int, default=10,
+                    help="deconvolution iterations timed in each precision form (0: operators only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precisions", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the differentiable and batched workloads")
@@ -478,6 +556,7 @@ def main():
                               "gmacs": round(2.0 * N * K / ((fm + am) * 1e-3) / 1e9, 1),
                               "tflops_slower_op": round(slow, 1), "peak": PEAK[pr],
                               "frac": round(slow / PEAK[pr], 4)}
+            precisions[pr].update(deconv_rate(nd, torch, y, h, x0, pr, args.precision_steps))
             if "fp32" in precisions:
                 precisions[pr]["pair_speedup_vs_fp32"] = round(
                     (precisions["fp32"]["forward_ms"] + precisions["fp32"]["transpose_ms"]) / (fm + am), 2)
@@ -503,6 +582,7 @@ def main():
         out["small_psf"] = bench_small_psf(nd, torch)
         log("small psf:", out["small_psf"])
         out["differentiable"] = bench_differentiable(nd, torch)
+        out["differentiable"]["refinement"] = bench_joint_refinement(nd, torch)
         log("differentiable:", out["differentiable"])
         out["batched"] = bench_batched(nd, torch, table=args.tuning_table)
         log("batched:", out["batched"])

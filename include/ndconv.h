@@ -96,6 +96,7 @@ NDC_API size_t conv_dH_workspace_bytes(int n, const int64_t *m, const int64_t *p
 NDC_API int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH,
                int dtype, void *ws, size_t ws_bytes, void *stream);
 
+
 /* Projected-gradient deconvolution (Steps 1-3 of the paper's algorithm,
  * gradient by Eq. 6 in its fused form A^T(AX - Y) + lambda X):
  *   minimise f(X) = 1/2 ||A X - Y||^2 + lambda/2 ||X||^2  s.t. X >= 0,
@@ -106,19 +107,32 @@ NDC_API int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X,
  *
  *  Y      extent m_i+2p_i, read.   H extent 2p_i+1, read.
  *  X      in: X^0 (caller's initial solution); out: X^{iters_done}.
- *  iters  accepted steps to run (>= 0).
+ *  iters  accepted steps to run (0 <= iters <= NDC_MAX_ITERS).
  *  ws     workspace of at least deconv_workspace_bytes() bytes, caller-owned,
  *         device memory; contents on entry are ignored.
  *  stats  nullable device array of 4*(iters+1) doubles: row k holds
  *         (f(X^k), delta used to reach X^k, rejected trials, ||X^k-X^{k-1}||);
  *         row 0 holds f(X^0).  Rows past iters_done are left untouched.
- *  info   nullable device array of 2 ints: (iters_done, status) with status
- *         0 = all steps done, 1 = stopped, no decrease within 30 halvings,
- *         NDC_ENONFINITE = stopped on a non-finite objective.
+ *  info   nullable device array of 2 ints: (iters_done, status), status one
+ *         of NDC_STOP_DONE, NDC_STOP_NO_DESCENT, NDC_STOP_TRIALS or
+ *         NDC_ENONFINITE (stopped on a non-finite objective).
  *
- * The call waits on `stream` between batches of launched steps to learn how
- * many steps were accepted (normally once per call); X, stats and info are
- * complete when it returns NDC_OK. */
+ * Every trial (the first one of a step and each halved retry) costs one
+ * forward convolution.  The call enqueues a fixed schedule of 2*iters + 30
+ * trial slots (none for iters = 0) and returns without waiting: the accept,
+ * halve and stop decisions are taken on the device, and slots after the run
+ * has stopped return at once.  A run that has used every slot before
+ * `iters` accepted steps stops with NDC_STOP_TRIALS; its accepted steps
+ * stand, and since the fixed first trial keeps no state across steps a
+ * second call from the returned X continues it exactly.  X, stats and info
+ * are complete once the stream reaches the end of the call's work; the call
+ * may be captured into a graph (each replay reruns the whole call). */
+enum {
+  NDC_STOP_DONE = 0,       /* iters accepted steps                              */
+  NDC_STOP_NO_DESCENT = 1, /* no trial decreased f within 30 halvings          */
+  NDC_STOP_TRIALS = 2      /* every enqueued trial slot used before iters steps */
+};
+#define NDC_MAX_ITERS (1 << 24)
 NDC_API size_t deconv_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype, int precision);
 NDC_API int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
                    int iters, double lambda, int dtype, int precision, void *ws, size_t ws_bytes,
@@ -136,30 +150,41 @@ NDC_API int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void
  *                     one extra forward convolution per iteration;
  *     NDC_STEP_BB     Barzilai-Borwein <s,s>/<s,y>, s = X^k - X^{k-1},
  *                     y = g^k - g^{k-1}; delta_0 on the first iteration of a
- *                     call.  A non-positive or non-finite quotient falls back
- *                     to delta_0.
+ *                     call.  f is quadratic, so <s,y> is summed as
+ *                     ||A s||^2 + lambda ||s||^2 + mu ||L s||^2 from a forward
+ *                     of the step (no extra convolution: each BB trial's
+ *                     forward is taken of X_t - X^k and added to the current
+ *                     residual).  A non-positive or non-finite quotient falls
+ *                     back to delta_0.
  *   mu:   weight of a Tikhonov-Miller term mu/2 ||L X||^2 (the regularised
  *         family the paper's introduction names; >= 0, 0 = off).  L is the
  *         full convolution by the discrete Laplacian over the problem's n
  *         axes (3^n stencil: -2n at the centre, +1 at the axis neighbours;
  *         zero outside X).  The gradient gains mu L^T L X and
  *         delta_0 = 1/(||H||_1^2 + lambda + mu (4n)^2).
+ *   max_trials: trial slots to enqueue (0 = 2*iters + 30 as deconv_iterate,
+ *         at most 2*NDC_MAX_ITERS + 30); a run that uses them all before
+ *         `iters` steps stops with NDC_STOP_TRIALS.  Each unused slot costs
+ *         a few launches that return at once, which is negligible next to a
+ *         convolution except on tiny problems.
  * With mu > 0 the workspace is deconv_workspace_bytes_ex(..., 1) (larger by
  * two (m+2)-extent arrays, one X-sized array and the stencil); with mu = 0 it
- * is deconv_workspace_bytes.  NDC_EINVAL for an unknown rule or a negative
- * or non-finite mu; otherwise errors as deconv_iterate. */
+ * is deconv_workspace_bytes.  NDC_EINVAL for an unknown rule, a negative or
+ * non-finite mu or a max_trials out of range; otherwise errors and
+ * asynchrony as deconv_iterate.  The BB rule keeps <s,s> and <s,y> of the
+ * last accepted step on the device; a new call starts again from delta_0. */
 enum { NDC_STEP_FIXED = 0, NDC_STEP_CAUCHY = 1, NDC_STEP_BB = 2 };
 NDC_API size_t deconv_workspace_bytes_ex(int n, const int64_t *m, const int64_t *p, int dtype, int precision,
                                          int regularised);
 NDC_API int deconv_iterate_ex(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
-                              int iters, double lambda, double mu, int dtype, int precision, int rule, void *ws,
-                              size_t ws_bytes, double *stats, int *info, void *stream);
+                              int iters, double lambda, double mu, int dtype, int precision, int rule,
+                              int max_trials, void *ws, size_t ws_bytes, double *stats, int *info, void *stream);
 
 /* Batched form: many independent 3-D volumes, each with its own extents m,
  * half-widths p and PSF, in persistent launches that walk one tile list for
  * the whole batch.  Every volume keeps its own step size and acceptance
- * decisions (the rule of deconv_iterate); one step of the whole batch is
- * captured once into a hipGraph and replayed per step.  FP32 only; every
+ * decisions (the rule of deconv_iterate); one trial slot of the whole batch
+ * is captured once into a hipGraph and replayed per slot.  FP32 only; every
  * PSF needs 3 <= 2p_x+1 <= 33 and 2p_y+1 <= 33.
  *
  *  ndc_batch_plan_create: m and p are count x 3 host arrays (z, y, x);
@@ -169,12 +194,22 @@ NDC_API int deconv_iterate_ex(int n, const int64_t *m, const int64_t *p, const v
  *    tables; destroy it with ndc_batch_plan_destroy.
  *  ndc_batch_conv_full / ndc_batch_conv_adjoint: the two operators of every
  *    volume in one persistent launch; the pointer arguments are host arrays
- *    of count device pointers.  They wait for the launch to finish.
+ *    of count device pointers, read before the call returns (a small kernel
+ *    receives them as launch arguments and writes the plan's device table).
  *  ndc_batch_deconv: `iters` accepted steps on every volume, X[v] updated in
  *    place; ws holds ndc_batch_workspace_bytes(); stats is NULL or a host
  *    array of count nullable device pointers (each 4*(iters+1) doubles, as in
  *    deconv_iterate); info is NULL or a device array of 2*count ints
- *    (iters_done, status) per volume.  Complete when it returns.
+ *    (iters_done, status) per volume.  The same fixed schedule of
+ *    2*iters + 30 trial slots as deconv_iterate, with the same stop codes.
+ *  All three only enqueue work on `stream` and may be captured into a graph
+ *  (inside a capture the step is enqueued kernel by kernel instead of as the
+ *  plan's own graph).  Calls with one plan share its device tables, so they
+ *  must be ordered on one stream; overlapping calls with one plan on
+ *  different streams race.  Every output is checked against every input and
+ *  every other output (NDC_EALIAS) and every pointer must be device memory
+ *  (NDC_EINVAL) before anything is enqueued.  ndc_batch_plan_destroy waits
+ *  for the device to finish outstanding work first.
  *  ndc_batch_plan_info: (forward tiles, transpose tiles, persistent grid,
  *    LDS bytes per work-group). */
 typedef struct ndc_batch_plan ndc_batch_plan;

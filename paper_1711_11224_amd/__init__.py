@@ -146,16 +146,35 @@ def deconv_workspace_bytes_ex(shape, psf_shape, dtype=torch.float32, precision="
 STEP_RULES = {"fixed": 0, "cauchy": 1, "bb": 2}
 
 
+def _check_out_buffer(t, name, dtype, min_numel):
+    """Caller-supplied device output of the deconvolution: checked before the
+    library writes min_numel elements of `dtype` through its pointer."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < min_numel:
+        raise ValueError("%s needs at least %d elements, got %d" % (name, min_numel, t.numel()))
+    if not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+
+
 def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=None, info=None, stream=None,
-                   rule="fixed", mu=0.0):
+                   rule="fixed", mu=0.0, max_trials=0):
     """Run `iters` accepted projected-gradient steps in place on X (Steps 1-3,
     delta accepted by f(X^{k+1}) < f(X^k)).  `rule` picks the first trial of
     each iteration: "fixed" (delta_0), "cauchy" or "bb"; `mu` weights the
-    Laplacian (Tikhonov-Miller) term mu/2 ||L X||^2 (see ndconv.h).
-    Returns (X, stats, info) with stats (iters+1, 4) float64 and info (2,)
-    int32 on the device."""
+    Laplacian (Tikhonov-Miller) term mu/2 ||L X||^2; `max_trials` bounds the
+    trial slots the call enqueues (0: 2*iters + 30; see ndconv.h).  Nothing
+    waits on the host.  Returns (X, stats, info) with stats (iters+1, 4)
+    float64 and info (2,) int32 = (iters_done, status) on the device."""
     if rule not in STEP_RULES:
         raise ValueError("rule must be one of %s" % sorted(STEP_RULES))
+    iters, max_trials = int(iters), int(max_trials)
+    if not 0 <= iters <= _native.NDC_MAX_ITERS:
+        raise ValueError("iters must be in [0, %d]" % _native.NDC_MAX_ITERS)
     for t, nm in ((Y, "Y"), (H, "H"), (X, "X")):
         _dev(t, nm)
     if not (Y.dtype == H.dtype == X.dtype):
@@ -167,18 +186,22 @@ def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=N
     need = lib.deconv_workspace_bytes_ex(n, mm, pp, dt, pr, 1 if mu > 0 else 0)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _check_out_buffer(ws, "ws", torch.uint8, need)
     if stats is None:
         stats = torch.full((iters + 1, 4), float("nan"), dtype=torch.float64, device=X.device)
+    _check_out_buffer(stats, "stats", torch.float64, 4 * (iters + 1))
     if info is None:
         info = torch.zeros(2, dtype=torch.int32, device=X.device)
-    if rule == "fixed" and mu == 0:
-        check(lib.deconv_iterate(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam), dt, pr,
+    _check_out_buffer(info, "info", torch.int32, 2)
+    if rule == "fixed" and mu == 0 and max_trials == 0:
+        check(lib.deconv_iterate(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), iters, float(lam), dt, pr,
                                  ws.data_ptr(), ws.numel() * ws.element_size(), stats.data_ptr(), info.data_ptr(),
                                  _stream(stream)), "deconv_iterate")
     else:
-        check(lib.deconv_iterate_ex(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), int(iters), float(lam),
-                                    float(mu), dt, pr, STEP_RULES[rule], ws.data_ptr(), ws.numel() * ws.element_size(),
-                                    stats.data_ptr(), info.data_ptr(), _stream(stream)), "deconv_iterate_ex")
+        check(lib.deconv_iterate_ex(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), iters, float(lam),
+                                    float(mu), dt, pr, STEP_RULES[rule], max_trials, ws.data_ptr(),
+                                    ws.numel() * ws.element_size(), stats.data_ptr(), info.data_ptr(),
+                                    _stream(stream)), "deconv_iterate_ex")
     return X, stats, info
 
 
@@ -191,7 +214,7 @@ def conv_adjoint(r, h, precision="native"):
     return conv_adjoint_nd(r.contiguous(), h.contiguous(), precision=precision)
 
 
-def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed", mu=0.0):
+def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed", mu=0.0, max_trials=0):
     """Projected-gradient deconvolution; x0 defaults to the flux-matching flat
     start max(sum Y, 0)/(N sum H).  Returns (x, stats, info)."""
     y, h = y.contiguous(), h.contiguous()
@@ -206,4 +229,4 @@ def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed", 
         x.fill_(float(val))
     else:
         x = x0.clone().contiguous()
-    return deconv_iterate(y, h, x, iters, lam=lam, precision=precision, rule=rule, mu=mu)
+    return deconv_iterate(y, h, x, iters, lam=lam, precision=precision, rule=rule, mu=mu, max_trials=max_trials)

@@ -12,6 +12,8 @@ NDC_OK, NDC_EINVAL, NDC_EUNSUPPORTED, NDC_EALIAS = 0, -1, -2, -3
 NDC_ENONFINITE, NDC_EDEVICE, NDC_EWORKSPACE = -4, -5, -6
 NDC_F32, NDC_F64 = 0, 1
 NDC_PREC_NATIVE, NDC_PREC_BF16, NDC_PREC_SPLIT_BF16 = 0, 1, 2
+NDC_STOP_DONE, NDC_STOP_NO_DESCENT, NDC_STOP_TRIALS = 0, 1, 2
+NDC_MAX_ITERS = 1 << 24
 
 EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_dH_nd",
            "deconv_workspace_bytes", "deconv_iterate", "deconv_workspace_bytes_ex", "deconv_iterate_ex", "ndc_batch_plan_create", "ndc_batch_plan_destroy",
@@ -48,7 +50,7 @@ def _load():
     lib.deconv_workspace_bytes_ex.argtypes = [c_int, i64p, i64p, c_int, c_int, c_int]
     lib.deconv_workspace_bytes_ex.restype = sz
     lib.deconv_iterate_ex.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, ctypes.c_double, ctypes.c_double, c_int,
-                                      c_int, c_int, vp, sz, vp, vp, vp]
+                                      c_int, c_int, c_int, vp, sz, vp, vp, vp]
     lib.deconv_iterate_ex.restype = c_int
     pvp = ctypes.POINTER(ctypes.c_void_p)
     lib.ndc_batch_plan_create.argtypes = [c_int, i64p, i64p, c_int, c_int, ctypes.POINTER(c_int), pvp]

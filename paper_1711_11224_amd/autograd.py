@@ -7,7 +7,9 @@ is hand-written: for an upstream gradient G (extent m+2p),
                                                       the template)
 Both run in the library's kernels.  GaussianPSF builds a normalised
 separable Gaussian from log-sigmas with ordinary torch ops, so autograd
-carries dH on to the sigmas (blind PSF refinement).
+carries dH on to the sigmas (blind PSF refinement).  JointRefiner
+alternates projected steps on X with optimizer steps on the sigmas, both
+from one backward pass of the loss 1/2 ||X (x) H(sigma) - Y||^2.
 """
 import torch
 
@@ -63,3 +65,37 @@ class GaussianPSF(torch.nn.Module):
             f = f / f.sum()
             h = f if h is None else h[..., None] * f
         return h.to(self.dtype).contiguous()
+
+
+class JointRefiner:
+    """Joint refinement of X and the PSF widths on 1/2 ||X (x) H(sigma) - Y||^2.
+
+    One step is one forward (ConvFull) and its hand-written backward, which
+    gives dX (the transpose) and dH (the PSF-gradient kernel; autograd carries
+    it on to log sigma through GaussianPSF).  Then X takes the projected
+    gradient step of the paper's method, X <- max(X - delta dX, 0) with
+    delta = 1/||H||_1^2 (at most 1/L, so the X step alone never increases the
+    loss), and the sigmas take one step of `opt`.
+
+    With X unknown the loss alone does not pin sigma down from below: for
+    any narrower Gaussian the true object blurred by the missing width is a
+    non-negative X with the same noise-free fit, and a narrower PSF lets X
+    follow more of the noise."""
+
+    def __init__(self, y, x0, psf_model, lr=0.05):
+        self.y = y
+        self.x = x0.detach().clone().contiguous()
+        self.psf = psf_model
+        self.opt = torch.optim.Adam(psf_model.parameters(), lr=lr)
+
+    def step(self):
+        self.opt.zero_grad()
+        x = self.x.requires_grad_(True)
+        h = self.psf()
+        loss = 0.5 * ((ConvFull.apply(x, h) - self.y) ** 2).sum()
+        loss.backward()
+        with torch.no_grad():  # delta stays on the device: no host wait per step
+            delta = (1.0 / h.detach().abs().sum(dtype=torch.float64) ** 2).to(x.dtype)
+            self.x = torch.clamp(x.detach() - delta * x.grad, min=0).contiguous()
+        self.opt.step()
+        return loss.detach()

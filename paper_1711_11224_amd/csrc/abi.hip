@@ -14,7 +14,7 @@ namespace ndc {
 size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision, int reg_ndim);
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
                double lambda, double mu, int ndim, int dtype, int precision, void *ws, double *stats, int *info,
-               int rule, hipStream_t s);
+               int rule, int slots, hipStream_t s);
 bool mfma_supported(const Geom &g, int dtype, int precision);
 bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype);
 size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype);
@@ -320,16 +320,22 @@ size_t deconv_workspace_bytes_ex(int n, const int64_t *m, const int64_t *p, int 
   return deconv_ws_bytes(E.m3, E.p3, dtype, precision, regularised ? n : 0);
 }
 
+// Trial slots enqueued by one call: `iters` accepted steps, one rejected
+// trial per step on average, and one full halving sequence.
+static int default_trials(int iters) { return iters > 0 ? 2 * iters + 30 : 0; }
+
 static int deconv_checked(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X,
-                          int iters, double lambda, double mu, int dtype, int precision, int rule, void *ws,
-                          size_t ws_bytes, double *stats, int *info, void *stream) {
+                          int iters, double lambda, double mu, int dtype, int precision, int rule, int max_trials,
+                          void *ws, size_t ws_bytes, double *stats, int *info, void *stream) {
   if (rule != NDC_STEP_FIXED && rule != NDC_STEP_CAUCHY && rule != NDC_STEP_BB) return NDC_EINVAL;
   if (!(mu >= 0.0) || !isfinite(mu)) return NDC_EINVAL;
   Extents E;
   int rc = prepare(n, m, p, dtype, precision, E);
   if (rc) return rc;
   if (!Y || !H || !X) return NDC_EINVAL;
-  if (iters < 0 || !(lambda >= 0.0) || !isfinite(lambda)) return NDC_EINVAL;
+  if (iters < 0 || iters > NDC_MAX_ITERS || !(lambda >= 0.0) || !isfinite(lambda)) return NDC_EINVAL;
+  if (max_trials < 0 || max_trials > 2 * NDC_MAX_ITERS + 30) return NDC_EINVAL;
+  const int slots = iters == 0 ? 0 : (max_trials > 0 ? max_trials : default_trials(iters));
   const size_t need = deconv_ws_bytes(E.m3, E.p3, dtype, precision, mu > 0.0 ? n : 0);
   if (!ws || ws_bytes < need) return NDC_EWORKSPACE;
   const size_t es = esize(dtype);
@@ -345,22 +351,22 @@ static int deconv_checked(int n, const int64_t *m, const int64_t *p, const void 
   }
   if (!device_ptr(Y) || !device_ptr(H) || !device_ptr(X) || !device_ptr(ws)) return NDC_EINVAL;
   if ((stats && !device_ptr(stats)) || (info && !device_ptr(info))) return NDC_EINVAL;
-  return deconv_run(E.m3, E.p3, Y, H, X, iters, lambda, mu, n, dtype, precision, ws, stats, info, rule,
+  return deconv_run(E.m3, E.p3, Y, H, X, iters, lambda, mu, n, dtype, precision, ws, stats, info, rule, slots,
                     (hipStream_t)stream);
 }
 
 int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
                    double lambda, int dtype, int precision, void *ws, size_t ws_bytes, double *stats, int *info,
                    void *stream) {
-  return deconv_checked(n, m, p, Y, H, X, iters, lambda, 0.0, dtype, precision, NDC_STEP_FIXED, ws, ws_bytes,
+  return deconv_checked(n, m, p, Y, H, X, iters, lambda, 0.0, dtype, precision, NDC_STEP_FIXED, 0, ws, ws_bytes,
                         stats, info, stream);
 }
 
 int deconv_iterate_ex(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
-                      double lambda, double mu, int dtype, int precision, int rule, void *ws, size_t ws_bytes,
-                      double *stats, int *info, void *stream) {
-  return deconv_checked(n, m, p, Y, H, X, iters, lambda, mu, dtype, precision, rule, ws, ws_bytes, stats, info,
-                        stream);
+                      double lambda, double mu, int dtype, int precision, int rule, int max_trials, void *ws,
+                      size_t ws_bytes, double *stats, int *info, void *stream) {
+  return deconv_checked(n, m, p, Y, H, X, iters, lambda, mu, dtype, precision, rule, max_trials, ws, ws_bytes,
+                        stats, info, stream);
 }
 
 }  // extern "C"

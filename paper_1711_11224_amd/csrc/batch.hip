@@ -1,10 +1,16 @@
 // Batched form: many independent volumes, each with its own extents, PSF,
 // step size and line search, through persistent launches (conv_batch.hip).
-// One deconvolution step for the whole batch is a fixed sequence
+// One deconvolution trial slot for the whole batch is a fixed sequence
 //   transpose+update (persistent) -> retry update -> forward+residual
 //   (persistent) -> per-volume decide -> per-volume commit
-// captured once into a hipGraph and replayed once per step.  Every kernel
-// reads the per-volume phase word and skips volumes with nothing to do.
+// captured once into a hipGraph and replayed for a fixed number of slots.
+// Every kernel reads the per-volume phase word and skips volumes with
+// nothing to do.
+//
+// The kernels find each volume's arrays in a device table.  A call writes
+// its pointers into that table with a small kernel that receives them as
+// launch arguments (copied when the launch is enqueued), so no host buffer
+// has to outlive the call and nothing waits on the host.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -53,6 +59,10 @@ __global__ __launch_bounds__(BT) void b_init_kernel(const BVol *vols, double lam
     st->iters = iters;
     st->jmax = jmax;
     st->accepted = 0;
+    st->rule = NDC_STEP_FIXED;
+    st->ss = 0.0;
+    st->sy = 0.0;
+    st->mu = 0.0;
   }
 }
 
@@ -192,6 +202,57 @@ __global__ __launch_bounds__(BT) void b_commit_kernel(const BVol *vols) {
   }
 }
 
+// Per-call pointers of up to BP_MAX volumes, passed by value.
+constexpr int BP_MAX = 48;
+struct BPatch {
+  int first, n, deconv, pad;
+  char *ws;                 // deconvolution workspace (deconv only)
+  const void *a[BP_MAX][5]; // conv: H, X, R; deconv: Y, H, X, stats, info
+};
+
+// Workspace offsets of one volume's arrays (deconvolution table).
+struct BOff {
+  size_t xt, g, r, rt;
+};
+
+// grid = 1: write one chunk of the call's pointers into the device table.
+__global__ void b_patch_kernel(BVol *vols, const BOff *off, size_t off_state, BPatch pa) {
+  for (int i = threadIdx.x; i < pa.n; i += blockDim.x) {
+    const int vi = pa.first + i;
+    BVol &v = vols[vi];
+    if (pa.deconv) {
+      v.Y = (const float *)pa.a[i][0];
+      v.H = (const float *)pa.a[i][1];
+      v.X = (float *)pa.a[i][2];
+      v.stats = (double *)pa.a[i][3];
+      v.info = pa.a[i][4] ? (int *)pa.a[i][4] + 2 * vi : nullptr;
+      v.Xt = (float *)(pa.ws + off[vi].xt);
+      v.G = (float *)(pa.ws + off[vi].g);
+      v.R = (float *)(pa.ws + off[vi].r);
+      v.Rt = (float *)(pa.ws + off[vi].rt);
+      v.st = (DState *)(pa.ws + off_state) + vi;
+    } else {
+      v.H = (const float *)pa.a[i][0];
+      v.X = (float *)pa.a[i][1];
+      v.R = (float *)pa.a[i][2];
+      v.st = nullptr;
+    }
+  }
+}
+
+// grid = count: a volume still running after the last trial slot stops with
+// NDC_STOP_TRIALS.
+__global__ void b_finish_kernel(const BVol *vols) {
+  const BVol &v = vols[blockIdx.x];
+  if (threadIdx.x != 0 || v.st->phase == PH_DONE) return;
+  v.st->status = NDC_STOP_TRIALS;
+  v.st->phase = PH_DONE;
+  if (v.info) {
+    v.info[0] = v.st->k;
+    v.info[1] = v.st->status;
+  }
+}
+
 }  // namespace
 
 struct ndc_batch_plan {
@@ -201,11 +262,12 @@ struct ndc_batch_plan {
   BTile *d_fwd = nullptr, *d_adj = nullptr;
   BVol *d_vols = nullptr;       // deconvolution table
   BVol *d_vols_conv = nullptr;  // convolution-only table
+  BOff *d_off = nullptr;        // workspace offsets per volume
   std::vector<BVol> h_vols, h_vols_conv;
   size_t lds_fwd = 0, lds_adj = 0;
   int grid = 512;
   // workspace layout
-  std::vector<size_t> off_xt, off_g, off_r, off_rt;
+  std::vector<BOff> off;
   size_t off_state = 0, off_pf = 0, off_pa = 0, off_pe = 0, ws_total = 0;
   // captured step
   hipStream_t cap = nullptr;
@@ -356,14 +418,16 @@ int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dty
     b.fwd_hi = fhi[v];
     b.adj_lo = alo[v];
     b.adj_hi = ahi[v];
-    P->off_xt.push_back(o);
+    BOff f;
+    f.xt = o;
     o += al256(sizeof(float) * n);
-    P->off_g.push_back(o);
+    f.g = o;
     o += al256(sizeof(float) * n);
-    P->off_r.push_back(o);
+    f.r = o;
     o += al256(sizeof(float) * ny);
-    P->off_rt.push_back(o);
+    f.rt = o;
     o += al256(sizeof(float) * ny);
+    P->off.push_back(f);
     const size_t lf = batch_lds_bytes(2 * b.p[2] + 1, 2 * b.p[1] + 1, mg);
     P->lds_fwd = std::max(P->lds_fwd, lf);
     P->lds_adj = std::max(P->lds_adj, lf);
@@ -374,6 +438,7 @@ int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dty
   if (!rc) rc = to_device(P->adj.data(), sizeof(BTile) * P->adj.size(), (void **)&P->d_adj);
   if (!rc) rc = to_device(P->h_vols.data(), sizeof(BVol) * count, (void **)&P->d_vols);
   if (!rc) rc = to_device(P->h_vols_conv.data(), sizeof(BVol) * count, (void **)&P->d_vols_conv);
+  if (!rc) rc = to_device(P->off.data(), sizeof(BOff) * count, (void **)&P->d_off);
   if (!rc && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) rc = NDC_EDEVICE;
   if (rc) {
     ndc_batch_plan_destroy(P);
@@ -385,12 +450,16 @@ int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dty
 
 void ndc_batch_plan_destroy(ndc_batch_plan *P) {
   if (!P) return;
+  // calls return before their work has run: let it finish before the
+  // tables it reads are freed
+  (void)hipDeviceSynchronize();
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->cap) (void)hipStreamDestroy(P->cap);
   (void)hipFree(P->d_fwd);
   (void)hipFree(P->d_adj);
   (void)hipFree(P->d_vols);
   (void)hipFree(P->d_vols_conv);
+  (void)hipFree(P->d_off);
   (void)hipGetLastError();
   delete P;
 }
@@ -406,34 +475,99 @@ int ndc_batch_plan_info(const ndc_batch_plan *P, int64_t *out4) {
   return NDC_OK;
 }
 
-static int batch_conv(ndc_batch_plan *P, const void *const *in, const void *const *H, void *const *out, bool forward,
-                      void *stream) {
+}  // extern "C"
+
+namespace {
+
+struct Span {
+  uintptr_t lo, hi;  // [lo, hi)
+};
+
+// Any overlap among the output spans, or between an input and an output.
+bool spans_alias(std::vector<Span> outs, const std::vector<Span> &ins) {
+  outs.erase(std::remove_if(outs.begin(), outs.end(), [](const Span &a) { return a.lo == a.hi; }), outs.end());
+  std::sort(outs.begin(), outs.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+  for (size_t i = 1; i < outs.size(); ++i)
+    if (outs[i].lo < outs[i - 1].hi) return true;
+  for (const Span &q : ins) {
+    if (q.lo == q.hi) continue;
+    // the output starting last at or before q.hi - 1, and the one after it
+    auto it = std::upper_bound(outs.begin(), outs.end(), q.hi - 1, [](uintptr_t v, const Span &a) { return v < a.lo; });
+    if (it != outs.begin() && std::prev(it)->hi > q.lo) return true;
+  }
+  return false;
+}
+
+Span span(const void *p, size_t bytes) { return Span{(uintptr_t)p, (uintptr_t)p + bytes}; }
+
+size_t psf_elems(const BVol &b) { return (size_t)(2 * b.p[0] + 1) * (2 * b.p[1] + 1) * (2 * b.p[2] + 1); }
+
+// Enqueue the pointer table update of one call (chunks of BP_MAX volumes).
+hipError_t patch_table(ndc_batch_plan *P, BVol *table, bool deconv, char *ws,
+                       const void *const *a0, const void *const *a1, const void *const *a2,
+                       const void *const *a3, const void *a4, hipStream_t s) {
+  for (int first = 0; first < P->count; first += BP_MAX) {
+    BPatch pa;
+    memset(&pa, 0, sizeof(pa));
+    pa.first = first;
+    pa.n = std::min(BP_MAX, P->count - first);
+    pa.deconv = deconv ? 1 : 0;
+    pa.ws = ws;
+    for (int i = 0; i < pa.n; ++i) {
+      const int v = first + i;
+      pa.a[i][0] = a0[v];
+      pa.a[i][1] = a1[v];
+      pa.a[i][2] = a2[v];
+      pa.a[i][3] = a3 ? a3[v] : nullptr;
+      pa.a[i][4] = a4;
+    }
+    hipLaunchKernelGGL(b_patch_kernel, dim3(1), dim3(64), 0, s, table, (const BOff *)P->d_off, P->off_state, pa);
+  }
+  return hipGetLastError();
+}
+
+// A pointer the current device can dereference (device or managed memory).
+bool on_device(const void *ptr) {
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged || at.type == hipMemoryTypeUnified;
+}
+
+int batch_conv(ndc_batch_plan *P, const void *const *in, const void *const *H, void *const *out, bool forward,
+               void *stream) {
   if (!P || !in || !H || !out) return NDC_EINVAL;
+  std::vector<Span> outs, ins;
   for (int v = 0; v < P->count; ++v) {
     if (!in[v] || !H[v] || !out[v]) return NDC_EINVAL;
-    BVol &b = P->h_vols_conv[v];
+    const BVol &b = P->h_vols_conv[v];
     const size_t nin = sizeof(float) * (forward ? b.n : b.ny), nout = sizeof(float) * (forward ? b.ny : b.n);
-    const size_t nh = sizeof(float) * (2 * b.p[0] + 1) * (2 * b.p[1] + 1) * (2 * b.p[2] + 1);
-    const uintptr_t o = (uintptr_t)out[v];
-    auto ov = [&](const void *q, size_t nq) { return o < (uintptr_t)q + nq && (uintptr_t)q < o + nout; };
-    if (ov(in[v], nin) || ov(H[v], nh)) return NDC_EALIAS;
-    b.H = (const float *)H[v];
-    b.X = forward ? (float *)in[v] : (float *)out[v];
-    b.R = forward ? (float *)out[v] : (float *)in[v];
-    b.st = nullptr;
+    outs.push_back(span(out[v], nout));
+    ins.push_back(span(in[v], nin));
+    ins.push_back(span(H[v], sizeof(float) * psf_elems(b)));
   }
+  if (spans_alias(outs, ins)) return NDC_EALIAS;
+  for (int v = 0; v < P->count; ++v)
+    if (!on_device(in[v]) || !on_device(H[v]) || !on_device(out[v])) return NDC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(P->d_vols_conv, P->h_vols_conv.data(), sizeof(BVol) * P->count, hipMemcpyHostToDevice, s) !=
-      hipSuccess)
+  // table fields: H, X (forward input / transpose output), R (the other one)
+  const void *const *xs = forward ? in : (const void *const *)out;
+  const void *const *rs = forward ? (const void *const *)out : in;
+  if (patch_table(P, P->d_vols_conv, false, nullptr, H, xs, rs, nullptr, nullptr, s) != hipSuccess)
     return NDC_EDEVICE;
   hipError_t e = forward ? launch_batch_conv(P->mg, P->d_vols_conv, P->d_fwd, (int)P->fwd.size(), BOP_FWD, nullptr,
                                              P->grid, P->lds_fwd, s)
                          : launch_batch_conv(P->mg, P->d_vols_conv, P->d_adj, (int)P->adj.size(), BOP_ADJ, nullptr,
                                              P->grid, P->lds_adj, s);
-  if (e != hipSuccess) return NDC_EDEVICE;
-  // the table must not change before the launch has read it
-  return hipStreamSynchronize(s) == hipSuccess ? NDC_OK : NDC_EDEVICE;
+  return e == hipSuccess ? NDC_OK : NDC_EDEVICE;
 }
+
+}  // namespace
+
+extern "C" {
 
 int ndc_batch_conv_full(ndc_batch_plan *P, const void *const *X, const void *const *H, void *const *Y, void *stream) {
   return batch_conv(P, X, H, Y, true, stream);
@@ -447,29 +581,31 @@ int ndc_batch_conv_adjoint(ndc_batch_plan *P, const void *const *R, const void *
 int ndc_batch_deconv(ndc_batch_plan *P, const void *const *Y, const void *const *H, void *const *X, int iters,
                      double lambda, void *ws, size_t ws_bytes, double *const *stats, int *info, void *stream) {
   if (!P || !Y || !H || !X) return NDC_EINVAL;
-  if (iters < 0 || !(lambda >= 0.0) || !isfinite(lambda)) return NDC_EINVAL;
+  if (iters < 0 || iters > NDC_MAX_ITERS || !(lambda >= 0.0) || !isfinite(lambda)) return NDC_EINVAL;
   if (!ws || ws_bytes < P->ws_total) return NDC_EWORKSPACE;
-  char *w = (char *)ws;
-  const uintptr_t wl = (uintptr_t)ws, wh = wl + P->ws_total;
+  // outputs: X[v], stats[v], info, ws; inputs: Y[v], H[v]
+  std::vector<Span> outs, ins;
+  outs.push_back(span(ws, P->ws_total));
+  if (info) outs.push_back(span(info, sizeof(int) * 2 * (size_t)P->count));
   for (int v = 0; v < P->count; ++v) {
     if (!Y[v] || !H[v] || !X[v]) return NDC_EINVAL;
-    BVol &b = P->h_vols[v];
-    const uintptr_t x = (uintptr_t)X[v];
-    if (x < wh && wl < x + sizeof(float) * b.n) return NDC_EALIAS;
-    b.Y = (const float *)Y[v];
-    b.H = (const float *)H[v];
-    b.X = (float *)X[v];
-    b.Xt = (float *)(w + P->off_xt[v]);
-    b.G = (float *)(w + P->off_g[v]);
-    b.R = (float *)(w + P->off_r[v]);
-    b.Rt = (float *)(w + P->off_rt[v]);
-    b.st = (DState *)(w + P->off_state) + v;
-    b.stats = stats ? stats[v] : nullptr;
-    b.info = info ? info + 2 * v : nullptr;
+    const BVol &b = P->h_vols[v];
+    outs.push_back(span(X[v], sizeof(float) * b.n));
+    if (stats && stats[v]) outs.push_back(span(stats[v], sizeof(double) * 4 * ((size_t)iters + 1)));
+    ins.push_back(span(Y[v], sizeof(float) * b.ny));
+    ins.push_back(span(H[v], sizeof(float) * psf_elems(b)));
   }
+  if (spans_alias(outs, ins)) return NDC_EALIAS;
+  if (!on_device(ws) || (info && !on_device(info))) return NDC_EINVAL;
+  for (int v = 0; v < P->count; ++v)
+    if (!on_device(Y[v]) || !on_device(H[v]) || !on_device(X[v]) || (stats && stats[v] && !on_device(stats[v])))
+      return NDC_EINVAL;
+
+  char *w = (char *)ws;
   hipStream_t s = (hipStream_t)stream;
   double *pf = (double *)(w + P->off_pf), *pe = (double *)(w + P->off_pe);
-  if (hipMemcpyAsync(P->d_vols, P->h_vols.data(), sizeof(BVol) * P->count, hipMemcpyHostToDevice, s) != hipSuccess)
+  if (patch_table(P, P->d_vols, true, w, (const void *const *)Y, (const void *const *)H, (const void *const *)X,
+                  (const void *const *)stats, info, s) != hipSuccess)
     return NDC_EDEVICE;
   hipLaunchKernelGGL(b_init_kernel, dim3(P->count), dim3(BT), 0, s, (const BVol *)P->d_vols, lambda, iters, 30);
   hipLaunchKernelGGL(b_sumsq_kernel, dim3(P->count * EB), dim3(BT), 0, s, (const BVol *)P->d_vols, pe);
@@ -480,41 +616,37 @@ int ndc_batch_deconv(ndc_batch_plan *P, const void *const *Y, const void *const 
                      (const double *)pe);
   if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
 
-  if (P->use_graph && P->exec_ws != ws) {  // capture one step against this workspace
+  // The step graph replays into the caller's stream unless that stream is
+  // itself being captured (then the step's kernels are enqueued directly).
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NDC_EDEVICE;
+  const bool graph = P->use_graph && cs == hipStreamCaptureStatusNone;
+  if (graph && P->exec_ws != ws) {  // capture one slot against this workspace
     if (P->exec) {
       (void)hipGraphExecDestroy(P->exec);
       P->exec = nullptr;
     }
-    hipGraph_t graph = nullptr;
+    hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return NDC_EDEVICE;
     const hipError_t le = launch_step(P, w, P->cap);
-    const hipError_t ce = hipStreamEndCapture(P->cap, &graph);
-    if (le != hipSuccess || ce != hipSuccess || !graph) return NDC_EDEVICE;
-    const hipError_t ie = hipGraphInstantiate(&P->exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
+    const hipError_t ce = hipStreamEndCapture(P->cap, &g);
+    if (le != hipSuccess || ce != hipSuccess || !g) return NDC_EDEVICE;
+    const hipError_t ie = hipGraphInstantiate(&P->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
     if (ie != hipSuccess) {
       P->exec = nullptr;
       return NDC_EDEVICE;
     }
     P->exec_ws = ws;
   }
-  std::vector<DState> hs(P->count);
-  int remaining = iters;
-  while (remaining > 0) {
-    for (int step = 0; step < remaining; ++step) {
-      const hipError_t e = P->use_graph ? hipGraphLaunch(P->exec, s) : launch_step(P, w, s);
-      if (e != hipSuccess) return NDC_EDEVICE;
-    }
-    if (hipMemcpyAsync(hs.data(), w + P->off_state, sizeof(DState) * P->count, hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-      return NDC_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return NDC_EDEVICE;
-    remaining = 0;
-    for (int v = 0; v < P->count; ++v)
-      if (hs[v].phase != PH_DONE) remaining = std::max(remaining, iters - hs[v].k);
+  // the same fixed schedule as deconv_iterate: 2*iters + 30 trial slots
+  const int slots = iters > 0 ? 2 * iters + 30 : 0;
+  for (int slot = 0; slot < slots; ++slot) {
+    const hipError_t e = graph ? hipGraphLaunch(P->exec, s) : launch_step(P, w, s);
+    if (e != hipSuccess) return NDC_EDEVICE;
   }
-  // the volume table is reused by the next call: wait until this one is done
-  return hipStreamSynchronize(s) == hipSuccess ? NDC_OK : NDC_EDEVICE;
+  hipLaunchKernelGGL(b_finish_kernel, dim3(P->count), dim3(64), 0, s, (const BVol *)P->d_vols);
+  return hipGetLastError() == hipSuccess ? NDC_OK : NDC_EDEVICE;
 }
 
 }  // extern "C"

@@ -94,14 +94,15 @@ size_t batch_lds_bytes(int kx, int ky, int mg) {
 
 hipError_t launch_batch_conv(int mg, const BVol *vols, const BTile *tiles, int ntiles, int op, double *part,
                              int grid, size_t lds_bytes, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
+  // raise the dynamic-LDS limit once per process; call_once makes
+  // concurrent first calls from several host threads safe
+  static std::once_flag lds_once;
+  std::call_once(lds_once, [] {
     const int cap = 160 * 1024 - 64;
     (void)hipFuncSetAttribute((const void *)batch_conv_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     (void)hipFuncSetAttribute((const void *)batch_conv_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     (void)hipGetLastError();
-    attr_set = true;
-  }
+  });
   if (mg == 2)
     hipLaunchKernelGGL(batch_conv_kernel<2>, dim3(grid), dim3(MT), lds_bytes, s, vols, tiles, ntiles, op, part);
   else

@@ -346,13 +346,14 @@ hipError_t launch_dh(const int64_t m3[3], const int64_t p3[3], int dtype, const 
   const int threads = ((d.ky * d.ncg + 63) / 64) * 64;
   const dim3 grid((unsigned)(d.kz * d.nsplit));
   const size_t lds = dh_lds_bytes(d, es);
-  static bool attr_set = false;  // allow up to 96 KB of LDS (idempotent)
-  if (!attr_set) {
+  // raise the dynamic-LDS limit once per process; call_once makes
+  // concurrent first calls from several host threads safe
+  static std::once_flag lds_once;
+  std::call_once(lds_once, [] {
     (void)hipFuncSetAttribute((const void *)dh_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     (void)hipFuncSetAttribute((const void *)dh_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     (void)hipGetLastError();
-    attr_set = true;
-  }
+  });
   if (dtype == NDC_F64)
     hipLaunchKernelGGL(dh_kernel<double>, grid, dim3(threads), lds, s, (const double *)X, (const double *)G,
                        (double *)ws, d);

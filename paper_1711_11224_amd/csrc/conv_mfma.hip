@@ -41,14 +41,15 @@ template <int KX, int PREC, int XB>
 hipError_t launch_kx_xb(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
   using S = MfmaShape<KX, XB>;
   const size_t lds = sizeof(float) * (size_t)S::lds_floats(g.ky, MG_DEFAULT, PREC);
-  static bool attr_set = false;  // allow the full LDS of a CU (idempotent)
-  if (!attr_set) {
+  // raise the dynamic-LDS limit once per process; call_once makes
+  // concurrent first calls from several host threads safe
+  static std::once_flag lds_once;
+  std::call_once(lds_once, [] {
     (void)hipFuncSetAttribute((const void *)conv_mfma_kernel<KX, PREC, XB>,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)(sizeof(float) * S::lds_floats(MAX_KY, MG_DEFAULT, PREC)));
     (void)hipGetLastError();
-    attr_set = true;
-  }
+  });
   const dim3 t = tile_counts(g, XB);
   const unsigned total = t.x * t.y * t.z;
   hipLaunchKernelGGL((conv_mfma_kernel<KX, PREC, XB>), dim3(total), dim3(MT), lds, s, (const float *)in,

@@ -388,14 +388,15 @@ int choose_nt(const Geom &g, int precision) {
 template <int NJ, int NT, int PREC>
 hipError_t launch_w(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
   const size_t lds = w_lds_bytes<NT>(g.ky, PREC == PREC_SPLIT_);
-  static bool attr_set = false;  // allow the full LDS of a CU (idempotent)
-  if (!attr_set) {
+  // raise the dynamic-LDS limit once per process; call_once makes
+  // concurrent first calls from several host threads safe
+  static std::once_flag lds_once;
+  std::call_once(lds_once, [] {
     (void)hipFuncSetAttribute((const void *)conv_mfma32_kernel<NJ, NT, PREC>,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)w_lds_bytes<NT>(WMAX_KY, PREC == PREC_SPLIT_));
     (void)hipGetLastError();
-    attr_set = true;
-  }
+  });
   const dim3 t = w_tiles(g, NT);
   hipLaunchKernelGGL((conv_mfma32_kernel<NJ, NT, PREC>), dim3(t.x * t.y * t.z), dim3(WT), lds, s,
                      (const float *)in, (const float *)H, (float *)out, g, ep, (int)t.x, (int)t.y);

@@ -1,28 +1,36 @@
 // Projected-gradient deconvolution (Steps 1-3 of the paper's algorithm) with
 // the step-size acceptance rule f(X^{k+1}) < f(X^k) decided on the device.
 //
-// One "step" is a fixed launch sequence whose kernels read the phase word in
-// device memory and return at once when they have nothing to do:
+// One trial slot is a fixed launch sequence whose kernels read the phase word
+// in device memory and return at once when they have nothing to do:
 //   1. transpose of R with the UPDATE epilogue   (phase NEW):   G, X_t, partials
 //   2. elementwise update with the halved delta  (phase RETRY): X_t, partials
 //   3. forward of X_t with the RESID epilogue    (NEW|RETRY):   R_t, partials
 //   4. decide (one work-group): f(X_t) < f(X^k) ? accept : halve delta
 //   5. commit (only right after an acceptance): X <- X_t, R <- R_t
-// Rejections happen only at rounding-level stationarity with the adopted
-// delta_0, so the host normally launches `iters` steps and waits once.
+// A call enqueues a fixed number of slots (the accepted steps plus room for
+// rejected trials) and never waits on the host: slots after the last step
+// find the phase DONE and return at once, and a closing kernel reports a run
+// that used every slot before reaching `iters` steps.  The whole call can
+// therefore be captured into a graph.
 //
 // With a Cauchy or Barzilai-Borwein first trial the gradient comes first and
 // the trial is computed from it on the device:
-//   1. transpose of R with the GRAD epilogue     (phase NEW):   G, <g,g>, <s,dg>
+//   1. transpose of R with the GRAD epilogue     (phase NEW):   G, <g,g>
 //   1b. forward of G with the NORM epilogue      (NEW, Cauchy): ||A g||^2
 //   1c. step (one work-group): delta from the rule, phase -> RETRY
-// and steps 2-5 follow as for a halved retry.
+// and steps 2-5 follow as for a halved retry.  With BB the update also stores
+// the step D = X_t - X and the trial forward is taken of D: the RINC epilogue
+// forms R_t = R + A D and ||A D||^2, so the BB denominator
+// <s, g^k - g^{k-1}> = ||A s||^2 + lambda ||s||^2 + mu ||L s||^2 (f is
+// quadratic) is summed from products of the step itself instead of from the
+// difference of two rounded gradients, which cancels as steps shrink.
 //
 // With the Tikhonov-Miller term mu/2 ||L X||^2 (L: full convolution by the
 // 3^n Laplacian stencil, through the same operators) the step also runs
 //   0. transpose of P = L X^k by the stencil      (NEW):  Q = L^T L X^k
 //      (the gradient epilogues add mu*Q)
-//   3b. forward of X_t by the stencil, SQR        (NEW|RETRY): P_t, ||P_t||^2
+//   3b. forward of X_t (BB: of D) by the stencil  (NEW|RETRY): P_t, ||P_t||^2
 // and commit also moves P <- P_t; f and the decision include mu/2 ||P||^2.
 #include <math.h>
 
@@ -73,6 +81,7 @@ __global__ __launch_bounds__(ET) void init_kernel(const T *__restrict__ H, int64
     st->accepted = 0;
     st->rule = rule;
     st->ss = 0.0;
+    st->sy = 0.0;
     st->mu = mu;
   }
 }
@@ -90,33 +99,26 @@ __global__ void laplacian_kernel(T *__restrict__ l, int kz, int ky, int kx, int 
   l[e] = off == 0 ? (T)(-2 * ndim) : (off == 1 ? (T)1 : (T)0);
 }
 
-template <typename T>
-__global__ __launch_bounds__(ET) void zero_kernel(T *__restrict__ a, T *__restrict__ b, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < n; i += (int64_t)gridDim.x * ET) {
-    a[i] = (T)0;
-    b[i] = (T)0;
-  }
-}
-
-// First trial of a Cauchy / BB iteration from the gradient partials (GRAD
-// epilogue: <g,g>, <s, g - g_old>) and, for Cauchy, ||A g||^2 (NORM epilogue).
+// First trial of a Cauchy / BB iteration.  Cauchy: <g,g> from the GRAD
+// epilogue's partials and ||A g||^2 (and ||L g||^2) from NORM forwards of g.
+// BB: <s,s> and <s,y> that decide_kernel kept from the last accepted step.
 __global__ __launch_bounds__(ET) void step_kernel(DState *st, const double *part_grad, int64_t ng,
                                                   const double *part_ag, int64_t na, const double *part_lg,
                                                   int64_t nl) {
   if (st->phase != PH_NEW) return;
   __shared__ double red[ET / 64][2];
-  const double gg = wg_sum(part_grad, ng, 0, red);
-  const double sy = wg_sum(part_grad, ng, 1, red);
-  const double ag = st->rule == NDC_STEP_CAUCHY ? wg_sum(part_ag, na, 0, red) : 0.0;
-  const double lg = (st->rule == NDC_STEP_CAUCHY && nl) ? wg_sum(part_lg, nl, 0, red) : 0.0;
+  const bool cauchy = st->rule == NDC_STEP_CAUCHY;  // uniform
+  const double gg = cauchy ? wg_sum(part_grad, ng, 0, red) : 0.0;
+  const double ag = cauchy ? wg_sum(part_ag, na, 0, red) : 0.0;
+  const double lg = (cauchy && nl) ? wg_sum(part_lg, nl, 0, red) : 0.0;
   if (threadIdx.x != 0) return;
   double num = 0.0, den = 0.0;
-  if (st->rule == NDC_STEP_CAUCHY) {
+  if (cauchy) {
     num = gg;
     den = ag + st->lambda * gg + st->mu * lg;
   } else if (st->k > 0) {  // BB; delta_0 on the first iteration of a call
     num = st->ss;
-    den = sy;
+    den = st->sy;
   }
   const double q = den > 0.0 ? num / den : 0.0;
   st->delta = (isfinite(q) && q > 0.0) ? q : st->delta0;
@@ -167,10 +169,12 @@ __global__ __launch_bounds__(ET) void f0_kernel(DState *st, const double *part_f
   }
 }
 
+// X_t = max(X - delta G, 0) for a retry (and every BB trial), with the
+// partials of ||X_t||^2 and ||X_t - X||^2; D (nullable) receives X_t - X.
 template <typename T>
 __global__ __launch_bounds__(ET) void update_kernel(const T *__restrict__ X, const T *__restrict__ G,
-                                                    T *__restrict__ Xt, int64_t n, const DState *st,
-                                                    double *part) {
+                                                    T *__restrict__ Xt, T *__restrict__ D, int64_t n,
+                                                    const DState *st, double *part) {
   if (st->phase != PH_RETRY) return;
   __shared__ double red[ET / 64][2];
   const T d = (T)st->delta;
@@ -179,6 +183,7 @@ __global__ __launch_bounds__(ET) void update_kernel(const T *__restrict__ X, con
     const T x = X[i];
     const T xt = proj_nonneg<T>(x - d * G[i]);
     Xt[i] = xt;
+    if (D) D[i] = xt - x;
     s0 += (double)xt * (double)xt;
     const double dd = (double)xt - (double)x;
     s1 += dd * dd;
@@ -205,6 +210,10 @@ __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *pa
   const double x2 = wg_sum(part_upd, nu, 0, red);
   const double dx2 = wg_sum(part_upd, nu, 1, red);
   const double l2 = nreg ? wg_sum(part_reg, nreg, 0, red) : 0.0;
+  // BB trials come from a forward of the step D (RINC): ||A D||^2, ||L D||^2
+  const bool bb = st->rule == NDC_STEP_BB;  // uniform
+  const double ad2 = bb ? wg_sum(part_fwd, nf, 1, red) : 0.0;
+  const double ld2 = (bb && nreg) ? wg_sum(part_reg, nreg, 1, red) : 0.0;
   if (threadIdx.x != 0) return;
   const double ft = 0.5 * r2 + 0.5 * st->lambda * x2 + 0.5 * st->mu * l2;
   if (!isfinite(ft)) {
@@ -222,6 +231,7 @@ __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *pa
     st->k = k;
     st->f_cur = ft;
     st->ss = dx2;
+    st->sy = ad2 + st->lambda * dx2 + st->mu * ld2;
     st->rej = 0;
     st->delta = st->delta0;
     st->accepted = 1;
@@ -243,19 +253,28 @@ __global__ __launch_bounds__(ET) void decide_kernel(DState *st, const double *pa
   }
 }
 
+// Closes a call: a run still going after its last trial slot stops with
+// status NDC_STOP_TRIALS (the accepted steps so far stand).
+__global__ void finish_kernel(DState *st, int *info) {
+  if (threadIdx.x != 0 || st->phase == PH_DONE) return;
+  st->status = NDC_STOP_TRIALS;
+  st->phase = PH_DONE;
+  if (info) {
+    info[0] = st->k;
+    info[1] = st->status;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(ET) void commit_kernel(const DState *st, T *__restrict__ X, const T *__restrict__ Xt,
                                                     int64_t n, T *__restrict__ R, const T *__restrict__ Rt,
-                                                    int64_t ny, T *__restrict__ S, T *__restrict__ P,
-                                                    const T *__restrict__ Pt, int64_t np) {
+                                                    int64_t ny, T *__restrict__ P, const T *__restrict__ Pt,
+                                                    int64_t np) {
   if (!st->accepted) return;
   int64_t m = n > ny ? n : ny;
   if (P && np > m) m = np;
   for (int64_t i = blockIdx.x * (int64_t)ET + threadIdx.x; i < m; i += (int64_t)gridDim.x * ET) {
-    if (i < n) {
-      if (S) S[i] = Xt[i] - X[i];  // BB: the accepted step
-      X[i] = Xt[i];
-    }
+    if (i < n) X[i] = Xt[i];
     if (i < ny) R[i] = Rt[i];
     if (P && i < np) P[i] = Pt[i];
   }
@@ -311,7 +330,7 @@ WsLayout layout(int64_t N, int64_t NY, size_t esz, int64_t nf, int64_t nu, const
   o += align256((size_t)NY * esz);
   L.rt = o;
   o += align256((size_t)NY * esz);
-  L.sbuf = o;  // accepted step X^k - X^{k-1} (Barzilai-Borwein rule)
+  L.sbuf = o;  // trial step D = X_t - X (Barzilai-Borwein rule)
   o += align256((size_t)N * esz);
   L.lap = L.part_reg = L.p = L.pt = L.q = 0;
   if (R.ndim) {
@@ -353,7 +372,7 @@ Sizes sizes_for(const int64_t m3[3], const int64_t p3[3], int dtype, int precisi
 template <typename T>
 int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *Xv, int iters,
              double lambda, double mu, int ndim, int dtype, int precision, void *ws, double *stats, int *info,
-             int rule, hipStream_t s) {
+             int rule, int slots, hipStream_t s) {
   const Sizes S = sizes_for(m3, p3, dtype, precision);
   const RegSizes RS = reg_sizes(m3, mu > 0.0 ? ndim : 0, dtype, precision);
   const int64_t nu = S.pa.nblocks > S.n_ew ? S.pa.nblocks : S.n_ew;
@@ -363,7 +382,7 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   double *part_fwd = (double *)(w + L.part_fwd);
   double *part_upd = (double *)(w + L.part_upd);
   T *X = (T *)Xv, *Xt = (T *)(w + L.xt), *G = (T *)(w + L.g), *R = (T *)(w + L.r), *Rt = (T *)(w + L.rt);
-  T *Sb = rule == NDC_STEP_BB ? (T *)(w + L.sbuf) : nullptr;
+  T *D = rule == NDC_STEP_BB ? (T *)(w + L.sbuf) : nullptr;
   const bool reg = RS.ndim > 0;
   T *lap = reg ? (T *)(w + L.lap) : nullptr, *P = reg ? (T *)(w + L.p) : nullptr;
   T *Pt = reg ? (T *)(w + L.pt) : nullptr, *Q = reg ? (T *)(w + L.q) : nullptr;
@@ -372,7 +391,6 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
 
   hipLaunchKernelGGL(init_kernel<T>, dim3(1), dim3(ET), 0, s, (const T *)H, S.NH, lambda, iters, 30, rule,
                      reg ? mu : 0.0, ndim, st);
-  if (Sb) hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, Sb, G, S.N);
   hipLaunchKernelGGL(sumsq_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, S.N, part_upd);
   Epi ef{};
   ef.mode = EPI_RESID;
@@ -410,7 +428,6 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   eg.part = part_upd;
   eg.phase = &st->phase;
   eg.phase_mask = 1 << PH_NEW;
-  eg.S = Sb;
   eg.Q = Q;
   eg.mu = mu;
   Epi en{};  // Cauchy: ||A g||^2
@@ -424,7 +441,7 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   eq.mode = EPI_STORE;
   eq.phase = &st->phase;
   eq.phase_mask = 1 << PH_NEW;
-  Epi et{};
+  Epi et{};  // trial residual R_t = A X_t - Y
   et.mode = EPI_RESID;
   et.Y = Y;
   et.part = part_fwd;
@@ -433,47 +450,53 @@ int deconv_t(const int64_t m3[3], const int64_t p3[3], const void *Y, const void
   Epi elt = el;  // P_t = L X_t for every trial
   elt.phase = &st->phase;
   elt.phase_mask = (1 << PH_NEW) | (1 << PH_RETRY);
+  Epi ed = et;  // BB: R_t = R + A D and ||A D||^2
+  ed.mode = EPI_RINC;
+  ed.B = R;
+  Epi eld = elt;  // BB: P_t = P + L D and ||L D||^2
+  eld.mode = EPI_RINC;
+  eld.B = P;
   int64_t ncm = S.NY > S.N ? S.NY : S.N;
   if (reg && RS.NP > ncm) ncm = RS.NP;
   const int64_t ncommit = ew_blocks(ncm);
 
-  int remaining = iters;
-  while (remaining > 0) {
-    for (int step = 0; step < remaining; ++step) {
-      if (reg && launch_conv(RS.pla, RS.gla, dtype, NDC_PREC_NATIVE, P, lap, Q, eq, s) != hipSuccess)
+  // A fixed schedule of trial slots, nothing read back on the host.
+  for (int slot = 0; slot < slots; ++slot) {
+    if (reg && launch_conv(RS.pla, RS.gla, dtype, NDC_PREC_NATIVE, P, lap, Q, eq, s) != hipSuccess)
+      return NDC_EDEVICE;
+    if (rule == NDC_STEP_FIXED) {
+      if (launch_conv(S.pa, S.ga, dtype, precision, R, H, Xt, ea, s) != hipSuccess) return NDC_EDEVICE;
+    } else {
+      if (launch_conv(S.pa, S.ga, dtype, precision, R, H, G, eg, s) != hipSuccess) return NDC_EDEVICE;
+      // (NORM stores nothing; R_t / P_t are passed as valid, unused outputs)
+      if (rule == NDC_STEP_CAUCHY && launch_conv(S.pf, S.gf, dtype, precision, G, H, Rt, en, s) != hipSuccess)
         return NDC_EDEVICE;
-      if (rule == NDC_STEP_FIXED) {
-        if (launch_conv(S.pa, S.ga, dtype, precision, R, H, Xt, ea, s) != hipSuccess) return NDC_EDEVICE;
-      } else {
-        if (launch_conv(S.pa, S.ga, dtype, precision, R, H, G, eg, s) != hipSuccess) return NDC_EDEVICE;
-        // (NORM stores nothing; R_t / P_t are passed as valid, unused outputs)
-        if (rule == NDC_STEP_CAUCHY && launch_conv(S.pf, S.gf, dtype, precision, G, H, Rt, en, s) != hipSuccess)
-          return NDC_EDEVICE;
-        if (rule == NDC_STEP_CAUCHY && reg &&
-            launch_conv(RS.pl, RS.gl, dtype, NDC_PREC_NATIVE, G, lap, Pt, enl, s) != hipSuccess)
-          return NDC_EDEVICE;
-        hipLaunchKernelGGL(step_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_upd, S.pa.nblocks,
-                           (const double *)part_fwd, S.pf.nblocks, (const double *)part_reg, nreg);
-      }
-      hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, (const T *)G, Xt,
-                         S.N, (const DState *)st, part_upd);
+      if (rule == NDC_STEP_CAUCHY && reg &&
+          launch_conv(RS.pl, RS.gl, dtype, NDC_PREC_NATIVE, G, lap, Pt, enl, s) != hipSuccess)
+        return NDC_EDEVICE;
+      hipLaunchKernelGGL(step_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_upd, S.pa.nblocks,
+                         (const double *)part_fwd, S.pf.nblocks, (const double *)part_reg, nreg);
+    }
+    hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)S.n_ew), dim3(ET), 0, s, (const T *)X, (const T *)G, Xt, D,
+                       S.N, (const DState *)st, part_upd);
+    if (D) {
+      if (launch_conv(S.pf, S.gf, dtype, precision, D, H, Rt, ed, s) != hipSuccess) return NDC_EDEVICE;
+      if (reg && launch_conv(RS.pl, RS.gl, dtype, NDC_PREC_NATIVE, D, lap, Pt, eld, s) != hipSuccess)
+        return NDC_EDEVICE;
+    } else {
       if (launch_conv(S.pf, S.gf, dtype, precision, Xt, H, Rt, et, s) != hipSuccess) return NDC_EDEVICE;
       if (reg && launch_conv(RS.pl, RS.gl, dtype, NDC_PREC_NATIVE, Xt, lap, Pt, elt, s) != hipSuccess)
         return NDC_EDEVICE;
-      hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_fwd, S.pf.nblocks,
-                         (const double *)part_upd, S.pa.nblocks, S.n_ew, (const double *)part_reg, nreg, stats,
-                         info);
-      hipLaunchKernelGGL(commit_kernel<T>, dim3((unsigned)ncommit), dim3(ET), 0, s, (const DState *)st, X,
-                         (const T *)Xt, S.N, R, (const T *)Rt, S.NY, Sb, P, (const T *)Pt, reg ? RS.NP : 0);
-      if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
     }
-    DState h;
-    if (hipMemcpyAsync(&h, st, sizeof(DState), hipMemcpyDeviceToHost, s) != hipSuccess) return NDC_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return NDC_EDEVICE;
-    if (h.phase == PH_DONE) break;
-    remaining = iters - h.k;
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(ET), 0, s, st, (const double *)part_fwd, S.pf.nblocks,
+                       (const double *)part_upd, S.pa.nblocks, S.n_ew, (const double *)part_reg, nreg, stats,
+                       info);
+    hipLaunchKernelGGL(commit_kernel<T>, dim3((unsigned)ncommit), dim3(ET), 0, s, (const DState *)st, X,
+                       (const T *)Xt, S.N, R, (const T *)Rt, S.NY, P, (const T *)Pt, reg ? RS.NP : 0);
+    if (hipGetLastError() != hipSuccess) return NDC_EDEVICE;
   }
-  return NDC_OK;
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, st, info);
+  return hipGetLastError() == hipSuccess ? NDC_OK : NDC_EDEVICE;
 }
 
 }  // namespace
@@ -488,10 +511,12 @@ size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int 
 
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
                double lambda, double mu, int ndim, int dtype, int precision, void *ws, double *stats, int *info,
-               int rule, hipStream_t s) {
+               int rule, int slots, hipStream_t s) {
   if (dtype == NDC_F64)
-    return deconv_t<double>(m3, p3, Y, H, X, iters, lambda, mu, ndim, dtype, precision, ws, stats, info, rule, s);
-  return deconv_t<float>(m3, p3, Y, H, X, iters, lambda, mu, ndim, dtype, precision, ws, stats, info, rule, s);
+    return deconv_t<double>(m3, p3, Y, H, X, iters, lambda, mu, ndim, dtype, precision, ws, stats, info, rule,
+                            slots, s);
+  return deconv_t<float>(m3, p3, Y, H, X, iters, lambda, mu, ndim, dtype, precision, ws, stats, info, rule, slots,
+                         s);
 }
 
 }  // namespace ndc

@@ -32,10 +32,13 @@ __device__ inline void apply_epilogue(T *out, int64_t idx, T acc, const Epi &ep,
   } else if (ep.mode == EPI_GRAD) {
     T g = acc + (T)ep.lambda * ((const T *)ep.X)[idx];
     if (ep.Q) g += (T)ep.mu * ((const T *)ep.Q)[idx];
-    const T g_old = out[idx];
     out[idx] = g;
     s0 += (double)g * (double)g;
-    if (ep.S) s1 += (double)((const T *)ep.S)[idx] * ((double)g - (double)g_old);
+  } else if (ep.mode == EPI_RINC) {
+    const T r = ((const T *)ep.B)[idx] + acc;
+    out[idx] = r;
+    s0 += (double)r * (double)r;
+    s1 += (double)acc * (double)acc;
   } else if (ep.mode == EPI_NORM) {
     s0 += (double)acc * (double)acc;
   } else if (ep.mode == EPI_SQR) {

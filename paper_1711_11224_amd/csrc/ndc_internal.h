@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/ndconv.h"
 
 namespace ndc {
@@ -22,7 +24,7 @@ struct Geom {
   int flip;              // Hc[t] = H[k-1-t] on every axis
 };
 
-enum EpiMode { EPI_STORE = 0, EPI_RESID = 1, EPI_UPDATE = 2, EPI_GRAD = 3, EPI_NORM = 4, EPI_SQR = 5 };
+enum EpiMode { EPI_STORE = 0, EPI_RESID = 1, EPI_UPDATE = 2, EPI_GRAD = 3, EPI_NORM = 4, EPI_SQR = 5, EPI_RINC = 6 };
 
 // Deconvolution phases kept on the device (see deconv.hip).
 enum Phase { PH_NEW = 0, PH_RETRY = 1, PH_DONE = 2 };
@@ -33,10 +35,13 @@ enum Phase { PH_NEW = 0, PH_RETRY = 1, PH_DONE = 2 };
 //   UPDATE: g = acc + lambda*X[i] (+ mu*Q[i] if Q); G[i] = g;
 //           xt = max(X[i] - delta*g, 0); out[i] = xt;
 //           part0 += xt^2, part1 += (xt - X[i])^2               (Step 2)
-//   GRAD  : g = acc + lambda*X[i] (+ mu*Q[i] if Q); g_old = out[i]; out[i] = g;
-//           part0 += g^2, part1 += S[i]*(g - g_old) if S          (first trials)
+//   GRAD  : g = acc + lambda*X[i] (+ mu*Q[i] if Q); out[i] = g;
+//           part0 += g^2                                        (first trials)
 //   NORM  : nothing stored; part0 += acc^2                      (||A g||^2)
 //   SQR   : out[i] = acc; part0 += acc^2                        (L X, ||L X||^2)
+//   RINC  : out[i] = B[i] + acc; part0 += out[i]^2, part1 += acc^2
+//           (acc = A d for a step d: the trial residual A(X+d) - Y from the
+//           current one, and ||A d||^2 without cancellation)
 // Partial sums are double, one pair per work-group, written without atomics.
 // If phase != nullptr the kernel runs only when (1 << *phase) & phase_mask.
 struct Epi {
@@ -49,9 +54,9 @@ struct Epi {
   double *part;
   const int *phase;
   int phase_mask;
-  const void *S;  // GRAD: previous accepted step X^k - X^{k-1}, or null
   const void *Q;  // UPDATE / GRAD: L^T L X (Tikhonov-Miller term), or null
   double mu;      // its weight
+  const void *B;  // RINC: the array the product is added to
 };
 
 struct DState {
@@ -67,8 +72,9 @@ struct DState {
   int jmax;        // trials per step
   int accepted;    // 1 right after an accepting decision (commit copies)
   int rule;        // first trial of each iteration: NDC_STEP_FIXED / CAUCHY / BB
-  double ss;       // BB: ||X^k - X^{k-1}||^2 of the last accepted step
+  double ss;       // BB: <s,s> of the last accepted step s = X^k - X^{k-1}
   double mu;       // Tikhonov-Miller weight (0: off)
+  double sy;       // BB: <s, g^k - g^{k-1}> = ||A s||^2 + lambda <s,s> + mu ||L s||^2
 };
 
 // Launch descriptors --------------------------------------------------------

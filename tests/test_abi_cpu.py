@@ -140,9 +140,42 @@ def test_deconv_ex_rejects_bad_rule_or_weight():
     """An unknown step rule or a negative / non-finite Laplacian weight is
     refused before any pointer is looked at."""
     for rule, mu in ((7, 0.0), (0, -1.0), (1, float("nan")), (2, float("inf"))):
-        rc = lib.deconv_iterate_ex(3, I([4, 4, 4]), I([1, 1, 1]), None, None, None, 1, 0.0, mu, F32, 0, rule, None,
-                                   0, None, None, None)
+        rc = lib.deconv_iterate_ex(3, I([4, 4, 4]), I([1, 1, 1]), None, None, None, 1, 0.0, mu, F32, 0, rule, 0,
+                                   None, 0, None, None, None)
         assert rc == -1
+
+
+def test_deconv_rejects_iteration_and_trial_counts_out_of_range():
+    """iters and max_trials are bounded (the schedule is enqueued up front);
+    both are checked before any pointer is looked at."""
+    big = nd.NDC_MAX_ITERS + 1
+    for iters, trials in ((-1, 0), (big, 0), (1, -1), (1, 2 * nd.NDC_MAX_ITERS + 31)):
+        rc = lib.deconv_iterate_ex(3, I([4, 4, 4]), I([1, 1, 1]), None, None, None, iters, 0.0, 0.0, F32, 0, 0,
+                                   trials, None, 0, None, None, None)
+        assert rc == -1
+    assert lib.deconv_iterate(3, I([4, 4, 4]), I([1, 1, 1]), None, None, None, big, 0.0, F32, 0, None, 0, None,
+                              None, None) == -1
+
+
+def test_deconv_binding_checks_caller_buffers():
+    """The binding refuses stats / info / workspace tensors of the wrong
+    dtype, layout or size before the library could write past them."""
+    import torch
+    from paper_1711_11224_amd import _check_out_buffer
+    with pytest.raises(ValueError):
+        _check_out_buffer(torch.zeros(8, dtype=torch.float32), "stats", torch.float64, 8)
+    with pytest.raises(ValueError):
+        _check_out_buffer(torch.zeros(7, dtype=torch.float64), "stats", torch.float64, 8)
+    with pytest.raises(ValueError):
+        _check_out_buffer(torch.zeros((4, 4), dtype=torch.float64).t(), "stats", torch.float64, 8)
+    with pytest.raises(ValueError):
+        _check_out_buffer(torch.zeros(2, dtype=torch.int64), "info", torch.int32, 2)
+    with pytest.raises(ValueError):
+        _check_out_buffer(torch.zeros(1, dtype=torch.int32), "info", torch.int32, 2)
+    with pytest.raises(TypeError):
+        _check_out_buffer(None, "info", torch.int32, 2)
+    with pytest.raises(TypeError):  # right dtype and size, but host memory
+        _check_out_buffer(torch.zeros(2, dtype=torch.int32), "info", torch.int32, 2)
 
 
 def test_deconv_workspace_grows_with_the_laplacian_term():

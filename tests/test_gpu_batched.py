@@ -164,6 +164,51 @@ def test_batch_graph_replays_equal_eager(nd):
         assert torch.equal(out[1][2], out[0][2])
 
 
+def test_batch_calls_capture_into_a_graph(nd):
+    """ndc_batch_deconv and the batched operators enqueue work only, so a
+    caller can capture them; replays from the same X^0 (restored eagerly in
+    between) equal eager calls bitwise."""
+    say("case batch capture")
+    rng = np.random.default_rng(14)
+    specs = SMALL[:3]
+    ys, hs, x0s = _deconv_inputs(rng, specs)
+    plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=(4, 2, 0, 1))
+    gy = [torch.from_numpy(a).cuda() for a in ys]
+    gh = [torch.from_numpy(a).cuda() for a in hs]
+    x0 = [torch.from_numpy(a).cuda() for a in x0s]
+    xe, se, ie = plan.deconv(gy, gh, [a.clone() for a in x0], 5)
+    ye = plan.conv_full(xe, gh)
+    torch.cuda.synchronize()
+    xe, se, ie, ye = [a.clone() for a in xe], [a.clone() for a in se], ie.clone(), [a.clone() for a in ye]
+    xs = [a.clone() for a in x0]
+    yo = [torch.empty_like(a) for a in ye]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            _, stats, info = plan.deconv(gy, gh, xs, 5)
+            plan.conv_full(xs, gh, ys=yo)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for a, b in zip(xs, x0):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(info, ie), rep
+        for a, b in zip(xs, xe):
+            assert torch.equal(a, b), rep
+        for a, b in zip(stats, se):
+            assert same(a, b), rep
+        for a, b in zip(yo, ye):
+            assert torch.equal(a, b), rep
+    del g
+    torch.cuda.synchronize()
+    plan.close()
+
+
 def test_batched_workload_64_volumes(nd):
     """The batched workload: 64 volumes of 32^3 .. 96x160x160 with their own
     Gaussian PSFs (odd extents 9..31 per axis), 50 steps in one plan with
