@@ -96,6 +96,21 @@ NDC_API size_t conv_dH_workspace_bytes(int n, const int64_t *m, const int64_t *p
 NDC_API int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH,
                int dtype, void *ws, size_t ws_bytes, void *stream);
 
+/* conv_dH_nd for callers that cannot allocate device memory (code under
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and result, bit for bit, with the split-K partials in a scratch
+ * array of NDC_DH_SCRATCH_BYTES that the library holds in device memory on
+ * each GPU it runs on, until the process ends.  The call allocates nothing.
+ * NDC_EWORKSPACE (before anything is enqueued) when the partials would need
+ * more than NDC_DH_SCRATCH_BYTES, i.e. when conv_dH_workspace_bytes() of
+ * the problem exceeds it (32 MiB covers, e.g., a 128x512x512 X with a
+ * 63x31x31 PSF); NDC_EDEVICE if the array's address cannot be obtained.
+ * The array holds no state between calls (every partial is written before
+ * it is read), but every call on one GPU uses the same array: calls that
+ * overlap in time on one GPU (different streams, or host threads) race. */
+#define NDC_DH_SCRATCH_BYTES ((size_t)1 << 25)
+NDC_API int conv_dH_nd_noalloc(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH,
+                               int dtype, void *stream);
 
 /* Projected-gradient deconvolution (Steps 1-3 of the paper's algorithm,
  * gradient by Eq. 6 in its fused form A^T(AX - Y) + lambda X):

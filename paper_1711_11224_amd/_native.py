@@ -15,7 +15,9 @@ NDC_PREC_NATIVE, NDC_PREC_BF16, NDC_PREC_SPLIT_BF16 = 0, 1, 2
 NDC_STOP_DONE, NDC_STOP_NO_DESCENT, NDC_STOP_TRIALS = 0, 1, 2
 NDC_MAX_ITERS = 1 << 24
 
-EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_dH_nd",
+NDC_DH_SCRATCH_BYTES = 1 << 25
+
+EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_dH_nd", "conv_dH_nd_noalloc",
            "deconv_workspace_bytes", "deconv_iterate", "deconv_workspace_bytes_ex", "deconv_iterate_ex", "ndc_batch_plan_create", "ndc_batch_plan_destroy",
            "ndc_batch_workspace_bytes", "ndc_batch_plan_info", "ndc_batch_conv_full", "ndc_batch_conv_adjoint",
            "ndc_batch_deconv", "ndc_strerror", "ndc_version")
@@ -42,6 +44,8 @@ def _load():
     lib.conv_dH_workspace_bytes.restype = sz
     lib.conv_dH_nd.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, vp, sz, vp]
     lib.conv_dH_nd.restype = c_int
+    lib.conv_dH_nd_noalloc.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, vp]
+    lib.conv_dH_nd_noalloc.restype = c_int
     lib.deconv_workspace_bytes.argtypes = [c_int, i64p, i64p, c_int, c_int]
     lib.deconv_workspace_bytes.restype = sz
     lib.deconv_iterate.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, ctypes.c_double, c_int, c_int,

@@ -277,8 +277,14 @@ size_t conv_dH_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dt
   return ks > 1 ? (size_t)ks * E.nh * esize(dtype) : 0;
 }
 
-int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH, int dtype,
-               void *ws, size_t ws_bytes, void *stream) {
+}  // extern "C"
+
+// conv_dH_nd's body.  With scratch_max > 0 the split-K partials go to the
+// library's own scratch array (conv_dH_nd_noalloc): `ws` is then obtained
+// only after every argument check, from get_scratch, and must fit in
+// scratch_max bytes.
+int ndc::dH_checked(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH, int dtype,
+                    void *ws, size_t ws_bytes, size_t scratch_max, void *(*get_scratch)(), void *stream) {
   Extents E;
   int rc = prepare(n, m, p, dtype, NDC_PREC_NATIVE, E);
   if (rc) return rc;
@@ -289,11 +295,21 @@ int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const v
   dH_split(E.m3, E.p3, g, ks, zc);
   const bool dedicated = dh_supported(E.m3, E.p3, dtype);
   const size_t need = dedicated ? dh_workspace_bytes(E.m3, E.p3, dtype) : (ks > 1 ? (size_t)ks * E.nh * es : 0);
-  if (need && (!ws || ws_bytes < need)) return NDC_EWORKSPACE;
+  if (scratch_max) {
+    if (need > scratch_max) return NDC_EWORKSPACE;
+  } else if (need && (!ws || ws_bytes < need)) {
+    return NDC_EWORKSPACE;
+  }
   if (overlap(dH, E.nh * es, X, E.nx * es) || overlap(dH, E.nh * es, G, E.ny * es)) return NDC_EALIAS;
-  if (need && (overlap(ws, need, X, E.nx * es) || overlap(ws, need, G, E.ny * es) || overlap(ws, need, dH, E.nh * es)))
+  if (!scratch_max && need &&
+      (overlap(ws, need, X, E.nx * es) || overlap(ws, need, G, E.ny * es) || overlap(ws, need, dH, E.nh * es)))
     return NDC_EALIAS;
-  if (!device_ptr(X) || !device_ptr(G) || !device_ptr(dH) || (need && !device_ptr(ws))) return NDC_EINVAL;
+  if (!device_ptr(X) || !device_ptr(G) || !device_ptr(dH) || (!scratch_max && need && !device_ptr(ws)))
+    return NDC_EINVAL;
+  if (scratch_max && need) {
+    ws = get_scratch();
+    if (!ws) return NDC_EDEVICE;
+  }
   Epi ep{};
   ep.mode = EPI_STORE;
   hipStream_t s = (hipStream_t)stream;
@@ -305,6 +321,13 @@ int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const v
   if (launch_conv_valu(g, dtype, NDC_PREC_NATIVE, G, X, ws, ep, ks, zc, s) != hipSuccess) return NDC_EDEVICE;
   if (launch_splitk_reduce(dtype, ws, dH, (int64_t)E.nh, ks, s) != hipSuccess) return NDC_EDEVICE;
   return NDC_OK;
+}
+
+extern "C" {
+
+int conv_dH_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH, int dtype,
+               void *ws, size_t ws_bytes, void *stream) {
+  return dH_checked(n, m, p, X, G, dH, dtype, ws, ws_bytes, 0, nullptr, stream);
 }
 
 size_t deconv_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype, int precision) {

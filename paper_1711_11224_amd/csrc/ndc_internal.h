@@ -107,6 +107,11 @@ struct BTile {
 
 enum BatchOp { BOP_FWD = 0, BOP_ADJ = 1, BOP_INIT = 2, BOP_STEP_FWD = 3, BOP_STEP_ADJ = 4 };
 
+// conv_dH_nd and conv_dH_nd_noalloc (abi.hip): scratch_max = 0 takes the
+// caller's workspace, otherwise get_scratch() supplies the partials' buffer.
+int dH_checked(int n, const int64_t *m, const int64_t *p, const void *X, const void *G, void *dH, int dtype,
+               void *ws, size_t ws_bytes, size_t scratch_max, void *(*get_scratch)(), void *stream);
+
 // Fold an n-D problem (n <= 3) into 3-D extents.
 bool fold3(int n, const int64_t *m, const int64_t *p, int64_t m3[3], int64_t p3[3]);
 Geom forward_geom(const int64_t m3[3], const int64_t p3[3]);
