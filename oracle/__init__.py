@@ -23,6 +23,10 @@ Functions and the passage each follows:
                        "Application to 2-dimensional deconvolution"
   deconv               Steps 1-3 with the step-size acceptance rule
                        f(X^{k+1}) < f(X^k), gradient by Eq. 6
+  richardson_lucy      the maximum-likelihood (Richardson-Lucy) iteration
+                       the paper compares against (Introduction; Fig. 2f),
+                       built from the same two operators
+  i_divergence         the Poisson negative log-likelihood it decreases
 
 Readings where the paper is silent (initial step, shrink factor, the
 regularisation weight) are stated in each docstring.
@@ -406,3 +410,43 @@ def deconv(y, h, x0, iters, lam=0.0, jmax=30, literal_eq6=False, deltas=None, ru
         s_prev, g_prev = xt - x, g
         x, f_k, done = xt, f_t, done + 1
     return x, np.array(stats), done, status
+
+
+def i_divergence(y, ax):
+    """I-divergence D(y || Ax) = sum_s y_s log(y_s / (Ax)_s) - y_s + (Ax)_s,
+    the Poisson negative log-likelihood up to a constant, with 0 log 0 = 0 and
+    +inf where (Ax)_s = 0 < y_s.  Meant for y >= 0."""
+    y, ax = _d(y), _d(ax)
+    pos = y > 0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(pos, y * np.log(np.where(pos, y, 1.0) / ax), 0.0)
+    t = np.where(pos & (ax <= 0), np.inf, t)
+    return float(np.sum(t - y + ax))
+
+
+def richardson_lucy(y, h, x0, iters):
+    """The Richardson-Lucy (maximum-likelihood) iteration with the paper's
+    operators:
+
+      X^{k+1} = X^k * A^T(Y / (A X^k)) / A^T 1
+
+    with A the full convolution (Property 1) and A^T its transpose (Property
+    2), 1 the all-ones array of Y's extent, and the ratio taken as 0 where
+    A X^k = 0 (such outputs receive nothing from X^k).  Preconditions: Y,
+    H, X^0 >= 0 and sum H > 0.
+
+    Returns (X^iters, divergences) with divergences[k] = D(Y || A X^k) for
+    k = 0..iters (i_divergence)."""
+    y, h = _d(y), _d(h)
+    x = _d(x0).copy()
+    norm = conv_adjoint(np.ones(y.shape), h)  # A^T 1
+    divs = []
+    for k in range(iters + 1):
+        ax = conv_full(x, h)
+        divs.append(i_divergence(y, ax))
+        if k == iters:
+            break
+        with np.errstate(divide="ignore", invalid="ignore"):
+            q = np.where(ax > 0, y / np.where(ax > 0, ax, 1.0), 0.0)
+        x = x * conv_adjoint(q, h) / norm
+    return x, np.array(divs)

@@ -471,3 +471,92 @@ def test_initial_delta_bounds_the_curvature_with_laplacian():
     L = oracle.explicit_A(m, oracle.laplacian(2))
     top = np.linalg.eigvalsh(A.T @ A + lam * np.eye(20) + mu * L.T @ L).max()
     assert oracle.initial_delta(h, lam, mu) <= 1.0 / top
+
+
+# ---- Richardson-Lucy with the same operators (the paper's comparison method) ----
+
+def _rl_problem(rng, m=(4, 7, 9), k=(3, 3, 5), clean=False):
+    h = rng.random(k) + 0.05
+    x_true = rng.random(m) + 0.1
+    y = oracle.conv_full(x_true, h)
+    if not clean:
+        y = rng.poisson(20.0 * y).astype(np.float64) / 20.0
+    return y, h, x_true
+
+
+def test_rl_normaliser_is_psf_sum():
+    """A^T 1 = sum H at every voxel: every tap of the transpose lands inside
+    Y's extent (Property 2), so the normaliser is a constant (exact on
+    integers)."""
+    h = RNG.integers(0, 5, (3, 5, 3)).astype(np.float64)
+    n = oracle.conv_adjoint(np.ones((6 + 2, 7 + 4, 5 + 2)), h)
+    assert n.shape == (6, 7, 5) and np.all(n == h.sum())
+
+
+def test_rl_delta_psf_one_step():
+    """With the delta PSF at its centre A X is X zero-padded by p, so one
+    step from any positive X^0 gives the crop of Y."""
+    rng = np.random.default_rng(61)
+    h = np.zeros((3, 5, 3))
+    h[1, 2, 1] = 1.0
+    y = rng.random((6, 9, 7))
+    x1, d = oracle.richardson_lucy(y, h, rng.random((4, 5, 5)) + 0.5, 1)
+    np.testing.assert_allclose(x1, y[1:5, 2:7, 1:6], rtol=1e-15, atol=0)
+    assert d[1] <= d[0]
+
+
+def test_rl_conserves_flux():
+    """sum X^{k+1} * sum H = sum of Y over the outputs A X^k reaches: the
+    update redistributes exactly the observed counts."""
+    rng = np.random.default_rng(62)
+    y, h, _ = _rl_problem(rng)
+    x0 = rng.random((4, 7, 9)) + 0.2
+    for iters in (1, 2, 5):
+        x, _ = oracle.richardson_lucy(y, h, x0, iters)
+        assert abs(x.sum() * h.sum() - y.sum()) <= 1e-12 * y.sum()
+
+
+def test_rl_true_object_is_a_fixed_point():
+    """Noise-free data: Y / (A X*) = 1 on the support, A^T 1 / sum H = 1, so
+    X* is returned unchanged."""
+    rng = np.random.default_rng(63)
+    y, h, x_true = _rl_problem(rng, clean=True)
+    x1, d = oracle.richardson_lucy(y, h, x_true, 3)
+    np.testing.assert_allclose(x1, x_true, rtol=1e-13, atol=0)
+    assert abs(d[0]) <= 1e-12 * y.sum()
+
+
+def test_rl_divergence_decreases_and_x_stays_nonnegative():
+    """RL is an EM iteration for the Poisson likelihood: the I-divergence
+    never increases and X stays non-negative."""
+    rng = np.random.default_rng(64)
+    y, h, _ = _rl_problem(rng, m=(5, 12, 12), k=(3, 5, 5))
+    x, d = oracle.richardson_lucy(y, h, np.full((5, 12, 12), y.sum() / (h.sum() * 720)), 25)
+    assert np.all(np.diff(d) <= 1e-12 * abs(d[0])) and d[-1] < d[0]
+    assert x.min() >= 0
+
+
+def test_rl_step_with_dense_operator():
+    """One step against A built densely by the block recursion of Property 1
+    (explicit_A, no convolution routine): X * A^T (Y / A X) / A^T 1."""
+    rng = np.random.default_rng(65)
+    m, k = (3, 4, 5), (3, 3, 3)
+    y, h, _ = _rl_problem(rng, m=m, k=k)
+    x0 = rng.random(m) + 0.3
+    A = oracle.explicit_A(m, h)
+    ax = A @ x0.ravel()
+    ref = x0.ravel() * (A.T @ (y.ravel() / ax)) / (A.T @ np.ones(A.shape[0]))
+    x1, d = oracle.richardson_lucy(y, h, x0, 1)
+    np.testing.assert_allclose(x1.ravel(), ref, rtol=1e-13, atol=0)
+    yv = y.ravel()
+    pos = yv > 0
+    dref = float(np.sum(yv[pos] * np.log(yv[pos] / ax[pos])) - yv.sum() + ax.sum())
+    assert abs(d[0] - dref) <= 1e-12 * abs(dref)
+
+
+def test_i_divergence_special_values():
+    """0 log 0 = 0; a positive count where the model is 0 is infinite; equal
+    arrays give 0."""
+    assert oracle.i_divergence(np.array([0.0, 2.0]), np.array([1.0, 2.0])) == 1.0
+    assert oracle.i_divergence(np.array([1.0]), np.array([0.0])) == np.inf
+    assert oracle.i_divergence(np.array([3.0, 0.5]), np.array([3.0, 0.5])) == 0.0
