@@ -309,6 +309,28 @@ def deconv_rate(nd, torch, y, h, x0, precision, steps):
             "ms_per_iter": round(ms / max(done, 1), 3), "f_after_steps": float(f[-1])}
 
 
+def bench_rl(nd, torch, y, h, x0, steps=10):
+    """Richardson-Lucy on the metric workload (Y clipped at 0: the method
+    needs non-negative data), `steps` iterations in one call: one forward
+    and one transpose per iteration, 2 N K multiply-adds."""
+    yp = torch.clamp(y, min=0)
+    nd.rl_iterate(yp, h, x0.clone(), 1)
+    x = x0.clone()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    _, st, info = nd.rl_iterate(yp, h, x, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = st.cpu().numpy()
+    N, K = x0.numel(), h.numel()
+    return {"steps": steps, "ms_per_iter": round(ms / steps, 3), "iters_per_s": round(steps / (ms * 1e-3), 3),
+            "gmacs": round(2.0 * N * K * steps / (ms * 1e-3) / 1e9, 1),
+            "divergence_first_last": [float(d[0]), float(d[-1])]}
+
+
 def bench_step_rules(nd, torch, y, h, x0, ws, steps=10, fixed_max=60):
     """First-trial rules of the projected-gradient iteration on the metric
     workload: time per step, objective after `steps` steps, and how many steps
@@ -383,6 +405,17 @@ def bench_paper_2d(nd, torch, iters=100):
                 torch.cuda.synchronize()
                 rec[rule] = {"ms_per_iter": round(e0.elapsed_time(e1) / iters, 4),
                              "snr_db": snr(xg.cpu().numpy()), "iters_done": int(info.cpu()[0])}
+            # Richardson-Lucy (the paper's comparison method) on max(Y, 0), from the flat start
+            yp = torch.clamp(yg, min=0)
+            xr = torch.from_numpy(synth.flat_start(np.maximum(y, 0), h, x.shape).astype(np.float32)).cuda()
+            nd.rl_iterate(yp, hg, xr.clone(), 2)  # warm-up
+            torch.cuda.synchronize()
+            e0.record(s)
+            _, st, info = nd.rl_iterate(yp, hg, xr, iters)
+            e1.record(s)
+            torch.cuda.synchronize()
+            rec["rl"] = {"ms_per_iter": round(e0.elapsed_time(e1) / iters, 4), "snr_db": snr(xr.cpu().numpy()),
+                         "iters_done": int(info.cpu()[0])}
             out["%s_std%g" % (name, std)] = rec
     return out
 
@@ -577,6 +610,8 @@ def main():
     if not args.no_extra:
         out["step_rules"] = bench_step_rules(nd, torch, y, h, x0, ws)
         log("step rules:", out["step_rules"])
+        out["richardson_lucy"] = bench_rl(nd, torch, y, h, x0)
+        log("richardson-lucy:", out["richardson_lucy"])
         out["paper_2d"] = bench_paper_2d(nd, torch)
         log("paper 2-D shapes:", out["paper_2d"])
         out["small_psf"] = bench_small_psf(nd, torch)

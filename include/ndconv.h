@@ -195,6 +195,32 @@ NDC_API int deconv_iterate_ex(int n, const int64_t *m, const int64_t *p, const v
                               int iters, double lambda, double mu, int dtype, int precision, int rule,
                               int max_trials, void *ws, size_t ws_bytes, double *stats, int *info, void *stream);
 
+/* Richardson-Lucy (maximum-likelihood) deconvolution, the method the paper
+ * compares its own against (Introduction; Fig. 2f), built from the same two
+ * operators (Property 1 and Property 2):
+ *   X^{k+1} = X^k * A^T(Y / (A X^k)) / A^T 1,   A^T 1 = sum H at every voxel,
+ * the ratio taken as 0 where A X^k = 0.  It decreases the I-divergence
+ * D(Y || A X) = sum Y log(Y / (A X)) - Y + A X (0 log 0 = 0), the Poisson
+ * negative log-likelihood up to a constant.  Preconditions (not checked on
+ * the host): Y >= 0, H >= 0 with sum H > 0, X^0 >= 0.
+ *
+ *  X      in: X^0; out: X^{iters}, updated in place.
+ *  iters  iterations (0 <= iters <= NDC_MAX_ITERS); iters + 1 forward and
+ *         iters transpose convolutions are enqueued, nothing waits on the host.
+ *  ws     at least rl_workspace_bytes() bytes of device memory (one
+ *         Y-sized array and small state), contents on entry ignored.
+ *  stats  nullable device array of iters+1 doubles: D(Y || A X^k), k = 0..iters.
+ *  info   nullable device array of 2 ints: (k of the last recorded
+ *         divergence, status) with status NDC_STOP_DONE, NDC_ENONFINITE (a
+ *         NaN divergence stopped the run; X holds the last iterate) or
+ *         NDC_EINVAL (sum H not positive and finite: nothing ran).
+ * Argument checks and aliasing rules as deconv_iterate; the call may be
+ * captured into a graph. */
+NDC_API size_t rl_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype, int precision);
+NDC_API int rl_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
+                       int dtype, int precision, void *ws, size_t ws_bytes, double *stats, int *info,
+                       void *stream);
+
 /* Batched form: many independent 3-D volumes, each with its own extents m,
  * half-widths p and PSF, in persistent launches that walk one tile list for
  * the whole batch.  Every volume keeps its own step size and acceptance

@@ -17,7 +17,7 @@ PRECISIONS = {"native": NDC_PREC_NATIVE, "fp32": NDC_PREC_NATIVE, "fp64": NDC_PR
               "bf16": NDC_PREC_BF16, "split_bf16": NDC_PREC_SPLIT_BF16}
 
 __all__ = ["conv_full_nd", "conv_adjoint_nd", "conv_dH_nd", "deconv_iterate", "deconv_workspace_bytes",
-           "deconv_workspace_bytes_ex",
+           "deconv_workspace_bytes_ex", "rl_iterate", "richardson_lucy",
            "conv_full", "conv_adjoint", "deconv", "NdcError", "strerror", "PRECISIONS"]
 
 
@@ -205,6 +205,38 @@ def deconv_iterate(Y, H, X, iters, lam=0.0, precision="native", ws=None, stats=N
     return X, stats, info
 
 
+def rl_iterate(Y, H, X, iters, precision="native", ws=None, stats=None, info=None, stream=None):
+    """`iters` Richardson-Lucy iterations in place on X (rl_iterate in
+    ndconv.h): X <- X * A^T(Y / A X) / sum H.  Nothing waits on the host.
+    Returns (X, stats, info): stats (iters+1,) float64 = D(Y || A X^k),
+    info (2,) int32 = (last k recorded, status) on the device."""
+    iters = int(iters)
+    if not 0 <= iters <= _native.NDC_MAX_ITERS:
+        raise ValueError("iters must be in [0, %d]" % _native.NDC_MAX_ITERS)
+    for t, nm in ((Y, "Y"), (H, "H"), (X, "X")):
+        _dev(t, nm)
+    if not (Y.dtype == H.dtype == X.dtype):
+        raise ValueError("Y, H and X must share a dtype")
+    p = _half_widths(H)
+    if list(Y.shape) != [a + 2 * b for a, b in zip(X.shape, p)]:
+        raise ValueError("Y must have extent m+2p")
+    n, mm, pp, dt, pr = X.dim(), i64_array(X.shape), i64_array(p), _dtype_code(X), _prec(precision)
+    need = lib.rl_workspace_bytes(n, mm, pp, dt, pr)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _check_out_buffer(ws, "ws", torch.uint8, need)
+    if stats is None:
+        stats = torch.full((iters + 1,), float("nan"), dtype=torch.float64, device=X.device)
+    _check_out_buffer(stats, "stats", torch.float64, iters + 1)
+    if info is None:
+        info = torch.zeros(2, dtype=torch.int32, device=X.device)
+    _check_out_buffer(info, "info", torch.int32, 2)
+    check(lib.rl_iterate(n, mm, pp, Y.data_ptr(), H.data_ptr(), X.data_ptr(), iters, dt, pr, ws.data_ptr(),
+                         ws.numel() * ws.element_size(), stats.data_ptr(), info.data_ptr(), _stream(stream)),
+          "rl_iterate")
+    return X, stats, info
+
+
 # Friendlier names ------------------------------------------------------------
 def conv_full(x, h, precision="native"):
     return conv_full_nd(x.contiguous(), h.contiguous(), precision=precision)
@@ -230,3 +262,21 @@ def deconv(y, h, x0=None, iters=100, lam=0.0, precision="native", rule="fixed", 
     else:
         x = x0.clone().contiguous()
     return deconv_iterate(y, h, x, iters, lam=lam, precision=precision, rule=rule, mu=mu, max_trials=max_trials)
+
+
+def richardson_lucy(y, h, x0=None, iters=100, precision="native"):
+    """Richardson-Lucy deconvolution; x0 defaults to the flux-matching flat
+    start max(sum Y, 0)/(N sum H).  Returns (x, stats, info)."""
+    y, h = y.contiguous(), h.contiguous()
+    p = _half_widths(h)
+    m = [a - 2 * b for a, b in zip(y.shape, p)]
+    if x0 is None:
+        n = 1
+        for v in m:
+            n *= v
+        val = torch.clamp(y.sum(dtype=torch.float64), min=0) / (n * h.sum(dtype=torch.float64))
+        x = torch.empty(m, dtype=y.dtype, device=y.device)
+        x.fill_(float(val))
+    else:
+        x = x0.clone().contiguous()
+    return rl_iterate(y, h, x, iters, precision=precision)

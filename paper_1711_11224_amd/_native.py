@@ -18,7 +18,8 @@ NDC_MAX_ITERS = 1 << 24
 NDC_DH_SCRATCH_BYTES = 1 << 25
 
 EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_dH_nd", "conv_dH_nd_noalloc",
-           "deconv_workspace_bytes", "deconv_iterate", "deconv_workspace_bytes_ex", "deconv_iterate_ex", "ndc_batch_plan_create", "ndc_batch_plan_destroy",
+           "deconv_workspace_bytes", "deconv_iterate", "deconv_workspace_bytes_ex", "deconv_iterate_ex",
+           "rl_workspace_bytes", "rl_iterate", "ndc_batch_plan_create", "ndc_batch_plan_destroy",
            "ndc_batch_workspace_bytes", "ndc_batch_plan_info", "ndc_batch_conv_full", "ndc_batch_conv_adjoint",
            "ndc_batch_deconv", "ndc_strerror", "ndc_version")
 
@@ -56,6 +57,10 @@ def _load():
     lib.deconv_iterate_ex.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, ctypes.c_double, ctypes.c_double, c_int,
                                       c_int, c_int, c_int, vp, sz, vp, vp, vp]
     lib.deconv_iterate_ex.restype = c_int
+    lib.rl_workspace_bytes.argtypes = [c_int, i64p, i64p, c_int, c_int]
+    lib.rl_workspace_bytes.restype = sz
+    lib.rl_iterate.argtypes = [c_int, i64p, i64p, vp, vp, vp, c_int, c_int, c_int, vp, sz, vp, vp, vp]
+    lib.rl_iterate.restype = c_int
     pvp = ctypes.POINTER(ctypes.c_void_p)
     lib.ndc_batch_plan_create.argtypes = [c_int, i64p, i64p, c_int, c_int, ctypes.POINTER(c_int), pvp]
     lib.ndc_batch_plan_create.restype = c_int

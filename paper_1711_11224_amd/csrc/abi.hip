@@ -15,6 +15,9 @@ size_t deconv_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int 
 int deconv_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters,
                double lambda, double mu, int ndim, int dtype, int precision, void *ws, double *stats, int *info,
                int rule, int slots, hipStream_t s);
+size_t rl_ws_bytes(const int64_t m3[3], const int64_t p3[3], int dtype, int precision);
+int rl_run(const int64_t m3[3], const int64_t p3[3], const void *Y, const void *H, void *X, int iters, int dtype,
+           int precision, void *ws, double *stats, int *info, hipStream_t s);
 bool mfma_supported(const Geom &g, int dtype, int precision);
 bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype);
 size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype);
@@ -383,6 +386,36 @@ int deconv_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, con
                    void *stream) {
   return deconv_checked(n, m, p, Y, H, X, iters, lambda, 0.0, dtype, precision, NDC_STEP_FIXED, 0, ws, ws_bytes,
                         stats, info, stream);
+}
+
+size_t rl_workspace_bytes(int n, const int64_t *m, const int64_t *p, int dtype, int precision) {
+  Extents E;
+  if (prepare(n, m, p, dtype, precision, E)) return 0;
+  return rl_ws_bytes(E.m3, E.p3, dtype, precision);
+}
+
+int rl_iterate(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,
+               int dtype, int precision, void *ws, size_t ws_bytes, double *stats, int *info, void *stream) {
+  Extents E;
+  int rc = prepare(n, m, p, dtype, precision, E);
+  if (rc) return rc;
+  if (!Y || !H || !X) return NDC_EINVAL;
+  if (iters < 0 || iters > NDC_MAX_ITERS) return NDC_EINVAL;
+  const size_t need = rl_ws_bytes(E.m3, E.p3, dtype, precision);
+  if (!ws || ws_bytes < need) return NDC_EWORKSPACE;
+  const size_t es = esize(dtype);
+  const size_t ns = stats ? ((size_t)iters + 1) * sizeof(double) : 0;
+  const size_t ni = info ? 2 * sizeof(int) : 0;
+  const void *outs[4] = {X, ws, stats, info};
+  const size_t outn[4] = {E.nx * es, need, ns, ni};
+  for (int i = 0; i < 4; ++i) {
+    if (overlap(outs[i], outn[i], Y, E.ny * es) || overlap(outs[i], outn[i], H, E.nh * es)) return NDC_EALIAS;
+    for (int j = i + 1; j < 4; ++j)
+      if (overlap(outs[i], outn[i], outs[j], outn[j])) return NDC_EALIAS;
+  }
+  if (!device_ptr(Y) || !device_ptr(H) || !device_ptr(X) || !device_ptr(ws)) return NDC_EINVAL;
+  if ((stats && !device_ptr(stats)) || (info && !device_ptr(info))) return NDC_EINVAL;
+  return rl_run(E.m3, E.p3, Y, H, X, iters, dtype, precision, ws, stats, info, (hipStream_t)stream);
 }
 
 int deconv_iterate_ex(int n, const int64_t *m, const int64_t *p, const void *Y, const void *H, void *X, int iters,

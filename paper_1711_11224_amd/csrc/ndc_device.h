@@ -39,6 +39,14 @@ __device__ inline void apply_epilogue(T *out, int64_t idx, T acc, const Epi &ep,
     out[idx] = r;
     s0 += (double)r * (double)r;
     s1 += (double)acc * (double)acc;
+  } else if (ep.mode == EPI_RLQ) {
+    const T y = ((const T *)ep.Y)[idx];
+    out[idx] = acc > (T)0 ? y / acc : (T)0;
+    // y log(y/a) - y + a with 0 log 0 = 0 (+inf where a = 0 < y)
+    const double yd = (double)y, ad = (double)acc;
+    s0 += (yd > 0.0 ? (ad > 0.0 ? yd * log(yd / ad) : INFINITY) : 0.0) - yd + ad;
+  } else if (ep.mode == EPI_RLX) {
+    out[idx] = out[idx] * acc * (T)(*ep.delta);
   } else if (ep.mode == EPI_NORM) {
     s0 += (double)acc * (double)acc;
   } else if (ep.mode == EPI_SQR) {

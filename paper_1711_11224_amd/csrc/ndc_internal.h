@@ -24,7 +24,10 @@ struct Geom {
   int flip;              // Hc[t] = H[k-1-t] on every axis
 };
 
-enum EpiMode { EPI_STORE = 0, EPI_RESID = 1, EPI_UPDATE = 2, EPI_GRAD = 3, EPI_NORM = 4, EPI_SQR = 5, EPI_RINC = 6 };
+enum EpiMode {
+  EPI_STORE = 0, EPI_RESID = 1, EPI_UPDATE = 2, EPI_GRAD = 3, EPI_NORM = 4, EPI_SQR = 5, EPI_RINC = 6,
+  EPI_RLQ = 7, EPI_RLX = 8
+};
 
 // Deconvolution phases kept on the device (see deconv.hip).
 enum Phase { PH_NEW = 0, PH_RETRY = 1, PH_DONE = 2 };
@@ -42,6 +45,9 @@ enum Phase { PH_NEW = 0, PH_RETRY = 1, PH_DONE = 2 };
 //   RINC  : out[i] = B[i] + acc; part0 += out[i]^2, part1 += acc^2
 //           (acc = A d for a step d: the trial residual A(X+d) - Y from the
 //           current one, and ||A d||^2 without cancellation)
+//   RLQ   : q = Y[i]/acc where acc > 0, else 0; out[i] = q;
+//           part0 += Y[i] log(Y[i]/acc) - Y[i] + acc             (I-divergence)
+//   RLX   : out[i] = out[i] * acc * (*delta)  (in place: X <- X A^T q / sum H)
 // Partial sums are double, one pair per work-group, written without atomics.
 // If phase != nullptr the kernel runs only when (1 << *phase) & phase_mask.
 struct Epi {
