@@ -36,6 +36,84 @@ TILE_SOURCES = ["paper_1711_11224_amd/csrc/conv_mfma.hip", "paper_1711_11224_amd
                 "include/ndconv.h"]
 
 
+EXTRA_LEGS = ("step_rules", "richardson_lucy", "paper_2d", "small_psf", "differentiable", "refinement", "batched")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_conv_128x512x512_psf63x31x31.json")
+TILE_KERNEL = "void ndc::conv_mfma_kernel<31, 0, 8>"
+
+
+def tile_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for p in TILE_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()
+
+
+def kernel_key_name(name):
+    """rocprofv3's demangled name without the argument list and anonymous
+    namespaces: 'void ndc::conv_mfma_kernel<31, 0, 8>'."""
+    name = name.replace("(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(name):  # cut at the '(' that opens the argument list
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0 and i > 0:
+            return name[:i]
+    return name
+
+
+def read_counter_csv(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc CSV:
+    [(kernel name, grid size, value summed over the dispatch's rows,
+    duration in ns)]."""
+    import csv
+    per = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            key = row["Dispatch_Id"]
+            name, grid = kernel_key_name(row["Kernel_Name"]), int(row["Grid_Size"])
+            dur = int(row["End_Timestamp"]) - int(row["Start_Timestamp"]) if row.get("End_Timestamp") else 0
+            v = per.get(key, (name, grid, 0.0, dur))
+            per[key] = (name, grid, v[2] + float(row["Counter_Value"]), dur)
+    return list(per.values())
+
+
+def write_traffic_record(fetch_csv, write_csv):
+    """The FP32 tile's HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE
+    passes (KiB per dispatch), each scaled by what the same counter reads for
+    the 1 GiB calibration copy (the largest copyBuffer dispatch), keyed by the
+    hash of the tile's sources so that bench.py drops them once those change."""
+    rec = {"csrc_sha256": tile_sources_sha256(), "kernels": {}}
+    for csv_path, counter, key in ((fetch_csv, "FETCH_SIZE", "fetch"), (write_csv, "WRITE_SIZE", "write")):
+        rows = read_counter_csv(csv_path, counter)
+        copies = [v for n, g, v, t in rows if "copyBuffer" in n]
+        if not copies:
+            raise SystemExit("no calibration copy in %s (run with --copy-calibration 1024)" % csv_path)
+        scale = 1048576.0 / max(copies)
+        rec["%s_scale" % key] = scale
+        # launches that did the work: a deconvolution call's trial slots after
+        # the run has stopped return at once (under a fifth of the longest)
+        longest = {}
+        for n, g, v, t in rows:
+            longest[(n, g)] = max(longest.get((n, g), 0), t)
+        acc = {}
+        for n, g, v, t in rows:
+            if n == TILE_KERNEL and t >= 0.2 * longest[(n, g)]:
+                acc.setdefault("%s/%d" % (n, g), []).append(v)
+        for k, vals in acc.items():
+            kib = float(np.mean(vals))
+            d = rec["kernels"].setdefault(k, {})
+            d["%s_kib" % key] = kib
+            d["read_bytes" if key == "fetch" else "write_bytes"] = kib * 1024.0 * scale
+    with open(TRAFFIC_RECORD, "w") as f:
+        json.dump(rec, f, indent=1)
+    log("wrote", TRAFFIC_RECORD)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -88,23 +166,17 @@ def time_pairs(nd, torch, x, h, precision, reps):
 
 def measured_traffic(kernel_key, forward=True):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
-    passes (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known
-    size), or None when the kernel's sources (TILE_SOURCES) changed since
-    they were taken.
+    record (written by --traffic-record), or None when the kernel's sources
+    (TILE_SOURCES) changed since the counters were taken.
     Both operators may run the same kernel instantiation; the forward launch
     is the one with the larger grid (its output extent m+2p exceeds m)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_conv_128x512x512_psf63x31x31.json")
     try:
-        rec = json.load(open(path))
+        rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for p in TILE_SOURCES:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
     k = sorted((int(key.split("/")[1]), v) for key, v in rec.get("kernels", {}).items()
                if key.split("/")[0] == kernel_key)
-    if rec.get("csrc_sha256") != h.hexdigest() or not k or len(k) > 2:
+    if rec.get("csrc_sha256") != tile_sources_sha256() or not k or len(k) > 2:
         return None
     k = k[-1][1] if forward else k[0][1]
     return int(k["read_bytes"] + k["write_bytes"])
@@ -513,7 +585,19 @@ def main():
     ap.add_argument("--tuning-table", default=None, help="autotuner table (default: the package's)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (scales HBM counters)")
+    ap.add_argument("--legs", default=",".join(EXTRA_LEGS),
+                    help="comma-separated extra legs to run (default: all of %s)" % ",".join(EXTRA_LEGS))
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the FP32 tile's HBM-traffic record from two rocprofv3 --pmc counter files "
+                         "(FETCH_SIZE and WRITE_SIZE passes with --copy-calibration 1024) and exit")
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(*args.traffic_record)
+        return
+    legs = set(l for l in args.legs.split(",") if l)
+    unknown = legs - set(EXTRA_LEGS)
+    if unknown:
+        ap.error("unknown legs: %s" % ",".join(sorted(unknown)))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the hot path here is single-GPU (no collectives); "
               "sharding over several GPUs is not built", file=sys.stderr)
@@ -578,7 +662,7 @@ def main():
 
     if prec == "fp32":
         # both operators run the 32 x 32 tile instantiation for this workload
-        roofline["traffic"] = measured_traffic("void ndc::conv_mfma_kernel<31, 0, 8>", fwd_ms >= adj_ms)
+        roofline["traffic"] = measured_traffic(TILE_KERNEL, fwd_ms >= adj_ms)
 
     precisions = {}
     if not args.no_precisions:
@@ -608,19 +692,27 @@ def main():
         "precisions": precisions,
     }
     if not args.no_extra:
-        out["step_rules"] = bench_step_rules(nd, torch, y, h, x0, ws)
-        log("step rules:", out["step_rules"])
-        out["richardson_lucy"] = bench_rl(nd, torch, y, h, x0)
-        log("richardson-lucy:", out["richardson_lucy"])
-        out["paper_2d"] = bench_paper_2d(nd, torch)
-        log("paper 2-D shapes:", out["paper_2d"])
-        out["small_psf"] = bench_small_psf(nd, torch)
-        log("small psf:", out["small_psf"])
-        out["differentiable"] = bench_differentiable(nd, torch)
-        out["differentiable"]["refinement"] = bench_joint_refinement(nd, torch)
-        log("differentiable:", out["differentiable"])
-        out["batched"] = bench_batched(nd, torch, table=args.tuning_table)
-        log("batched:", out["batched"])
+        if "step_rules" in legs:
+            out["step_rules"] = bench_step_rules(nd, torch, y, h, x0, ws)
+            log("step rules:", out["step_rules"])
+        if "richardson_lucy" in legs:
+            out["richardson_lucy"] = bench_rl(nd, torch, y, h, x0)
+            log("richardson-lucy:", out["richardson_lucy"])
+        if "paper_2d" in legs:
+            out["paper_2d"] = bench_paper_2d(nd, torch)
+            log("paper 2-D shapes:", out["paper_2d"])
+        if "small_psf" in legs:
+            out["small_psf"] = bench_small_psf(nd, torch)
+            log("small psf:", out["small_psf"])
+        if "differentiable" in legs:
+            out["differentiable"] = bench_differentiable(nd, torch)
+            log("differentiable:", out["differentiable"])
+        if "refinement" in legs:
+            out.setdefault("differentiable", {})["refinement"] = bench_joint_refinement(nd, torch)
+            log("refinement:", out["differentiable"]["refinement"])
+        if "batched" in legs:
+            out["batched"] = bench_batched(nd, torch, table=args.tuning_table)
+            log("batched:", out["batched"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, nd, torch)
     print(json.dumps(out), flush=True)
