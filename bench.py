@@ -583,6 +583,9 @@ def main():
     ap.add_argument("--no-precisions", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the differentiable and batched workloads")
     ap.add_argument("--tuning-table", default=None, help="autotuner table (default: the package's)")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every kernel form of the workload's two operators in each precision and store the "
+                         "fastest in the tuning table (otherwise the table's choices are installed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (scales HBM counters)")
     ap.add_argument("--legs", default=",".join(EXTRA_LEGS),
@@ -611,7 +614,19 @@ def main():
     cfg = synth.CONFIGS["c3_metric"]
     N = int(np.prod(cfg.shape))
     K = int(np.prod(cfg.psf_shape))
+    from paper_1711_11224_amd import autotune
     y, h, x0 = make_inputs(nd, torch, cfg, dev)
+    if args.retune:
+        # the workload's own operands: X^0 for the forward, its residual for the transpose
+        r0 = nd.conv_full_nd(x0, h) - y
+        for pr in ("fp32", "bf16", "split_bf16"):
+            res = autotune.tune_conv(cfg.shape, cfg.psf_shape, pr, table=args.tuning_table, x=x0, h=h, r=r0)
+            log("tuned %s:" % pr, {op: res[op][0] for op in res}, {op: res[op][1] for op in res})
+        del r0
+    else:
+        log("kernel forms installed from the tuning table:", autotune.apply_table(args.tuning_table))
+    tile_forms = {pr: {op: list(autotune.current_form(cfg.shape, cfg.psf_shape, op, pr)) for op in autotune.OPS}
+                  for pr in ("fp32", "bf16", "split_bf16")}
     if args.copy_calibration > 0:
         nb = args.copy_calibration << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
@@ -690,6 +705,7 @@ def main():
                    "conv_pair_gmacs": round(pair_gmacs, 1), "macs_per_step": 2 * N * K},
         "roofline": roofline,
         "precisions": precisions,
+        "tile_forms": tile_forms,
     }
     if not args.no_extra:
         if "step_rules" in legs:

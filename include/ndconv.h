@@ -267,6 +267,36 @@ NDC_API int ndc_batch_deconv(ndc_batch_plan *plan, const void *const *Y, const v
                              int iters, double lambda, void *ws, size_t ws_bytes, double *const *stats, int *info,
                              void *stream);
 
+/* Kernel form per problem (the autotuner's hook).  Each operator of a
+ * problem runs one of the library's kernel forms; by default a built-in rule
+ * picks it from the PSF and volume size.  ndc_tile_override replaces that
+ * choice for one exact problem (n, m, p, dtype, precision) and operator (op
+ * 0 = forward conv_full_nd, 1 = transpose conv_adjoint_nd) wherever the
+ * library runs that operator (the operators, deconv_iterate, rl_iterate):
+ *   NDC_FORM_AUTO    remove the override (built-in rule);
+ *   NDC_FORM_VALU    the general vector-ALU kernel (every problem);
+ *   NDC_FORM_SMALL   the small-PSF streaming kernel (every axis <= 7 taps,
+ *                    native precision);
+ *   NDC_FORM_MFMA4   the 4x4x1 matrix-core tile, param = x-blocks per
+ *                    instruction: 8 (32x32 outputs per wave group) or 16
+ *                    (16x64, native precision only); 3 <= 2p_x+1 <= 33;
+ *   NDC_FORM_MFMA32  the 32x32x16 bf16 tile (bf16 forms, 11 <= 2p_x+1 <= 33),
+ *                    param = 32x32 blocks per wave along x, 2..4 (split-bf16:
+ *                    2..3).
+ * NDC_EUNSUPPORTED if the form cannot run the problem (or the table, of
+ * NDC_MAX_TILE_OVERRIDES entries, is full).  Every form computes the same
+ * operator; results agree within the precision's rounding.  The table is
+ * process-wide and guarded by a lock; a workspace sized before an override
+ * changed a plan is checked again by each call.  ndc_tile_choice reports the
+ * form and parameter the library would use now, as out2[0..1]. */
+enum { NDC_FORM_AUTO = 0, NDC_FORM_VALU = 1, NDC_FORM_SMALL = 2, NDC_FORM_MFMA4 = 3, NDC_FORM_MFMA32 = 4 };
+#define NDC_MAX_TILE_OVERRIDES 4096
+NDC_API int ndc_tile_override(int n, const int64_t *m, const int64_t *p, int dtype, int precision, int op,
+                              int form, int param);
+NDC_API void ndc_tile_override_clear(void);
+NDC_API int ndc_tile_choice(int n, const int64_t *m, const int64_t *p, int dtype, int precision, int op,
+                            int *out2);
+
 /* Static text for a status code (never NULL). */
 NDC_API const char *ndc_strerror(int status);
 

@@ -21,7 +21,9 @@ EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_d
            "deconv_workspace_bytes", "deconv_iterate", "deconv_workspace_bytes_ex", "deconv_iterate_ex",
            "rl_workspace_bytes", "rl_iterate", "ndc_batch_plan_create", "ndc_batch_plan_destroy",
            "ndc_batch_workspace_bytes", "ndc_batch_plan_info", "ndc_batch_conv_full", "ndc_batch_conv_adjoint",
-           "ndc_batch_deconv", "ndc_strerror", "ndc_version")
+           "ndc_batch_deconv", "ndc_tile_override", "ndc_tile_override_clear", "ndc_tile_choice", "ndc_strerror",
+           "ndc_version")
+NDC_FORM_AUTO, NDC_FORM_VALU, NDC_FORM_SMALL, NDC_FORM_MFMA4, NDC_FORM_MFMA32 = 0, 1, 2, 3, 4
 
 
 class NdcError(RuntimeError):
@@ -76,6 +78,12 @@ def _load():
     lib.ndc_batch_conv_adjoint.restype = c_int
     lib.ndc_batch_deconv.argtypes = [vp, pvp, pvp, pvp, c_int, ctypes.c_double, vp, sz, pvp, vp, vp]
     lib.ndc_batch_deconv.restype = c_int
+    lib.ndc_tile_override.argtypes = [c_int, i64p, i64p, c_int, c_int, c_int, c_int, c_int]
+    lib.ndc_tile_override.restype = c_int
+    lib.ndc_tile_override_clear.argtypes = []
+    lib.ndc_tile_override_clear.restype = None
+    lib.ndc_tile_choice.argtypes = [c_int, i64p, i64p, c_int, c_int, c_int, ctypes.POINTER(c_int)]
+    lib.ndc_tile_choice.restype = c_int
     lib.ndc_strerror.argtypes = [c_int]
     lib.ndc_strerror.restype = ctypes.c_char_p
     lib.ndc_version.argtypes = []

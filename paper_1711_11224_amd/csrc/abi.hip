@@ -3,6 +3,9 @@
 // enqueued; nothing here throws, aborts or allocates device memory.
 #include <limits.h>
 #include <math.h>
+
+#include <mutex>
+#include <vector>
 #include <stdlib.h>
 #include <string.h>
 
@@ -23,11 +26,13 @@ bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype);
 size_t dh_workspace_bytes(const int64_t m3[3], const int64_t p3[3], int dtype);
 hipError_t launch_dh(const int64_t m3[3], const int64_t p3[3], int dtype, const void *X, const void *G, void *dH,
                      void *ws, hipStream_t s);
-ConvPlan plan_conv_mfma(const Geom &g, int dtype, int precision);
+ConvPlan plan_conv_mfma(const Geom &g, int dtype, int precision, int xb);
 bool mfma32_supported(const Geom &g, int dtype, int precision);
-ConvPlan plan_conv_mfma32(const Geom &g, int precision);
-hipError_t launch_conv_mfma32(const Geom &g, int precision, const void *in, const void *H, void *out,
-                              const Epi &ep, hipStream_t s);
+bool mfma32_fits(const Geom &g, int dtype, int precision);
+bool mfma32_nt_ok(int nt, int precision);
+ConvPlan plan_conv_mfma32(const Geom &g, int precision, int nt);
+hipError_t launch_conv_mfma32(const ConvPlan &pl, const Geom &g, int precision, const void *in, const void *H,
+                              void *out, const Epi &ep, hipStream_t s);
 bool small_supported(const Geom &g, int dtype, int precision);
 int64_t small_blocks(const Geom &g, int dtype);
 hipError_t launch_conv_small(const Geom &g, int dtype, const void *in, const void *H, void *out, const Epi &ep,
@@ -89,36 +94,95 @@ static int64_t grid_blocks(dim3 g) { return (int64_t)g.x * g.y * g.z; }
 // width fits the MFMA tile (the bf16 forms of rows 11..33 taps wide on the
 // 32x32x16 instruction, the rest on the 4x4 forms); everything else takes
 // the general VALU kernel.
-static bool use_small(const Geom &g, int dtype, int precision) {
-  return g.kx <= 7 && g.ky <= 7 && g.kz <= 7 && small_supported(g, dtype, precision) && !getenv("NDC_FORCE_VALU");
+static bool small_fits(const Geom &g, int dtype, int precision) {
+  return g.kx <= 7 && g.ky <= 7 && g.kz <= 7 && small_supported(g, dtype, precision);
 }
 
-ConvPlan plan_conv(const Geom &g, int dtype, int precision) {
-  if (use_small(g, dtype, precision)) {
-    ConvPlan pl;
-    pl.variant = 2;
-    pl.nblocks = small_blocks(g, dtype);
-    pl.grid = dim3((unsigned)pl.nblocks);
-    pl.block = dim3(256);
-    pl.lds_bytes = 0;
-    return pl;
-  }
-  if (mfma32_supported(g, dtype, precision) && mfma_supported(g, dtype, precision)) return plan_conv_mfma32(g, precision);
-  if (mfma_supported(g, dtype, precision)) return plan_conv_mfma(g, dtype, precision);
-  ConvPlan pl;
+static bool use_small(const Geom &g, int dtype, int precision) {
+  return small_fits(g, dtype, precision) && !getenv("NDC_FORCE_VALU");
+}
+
+static ConvPlan plan_small(const Geom &g, int dtype) {
+  ConvPlan pl{};
+  pl.variant = 2;
+  pl.nblocks = small_blocks(g, dtype);
+  pl.grid = dim3((unsigned)pl.nblocks);
+  pl.block = dim3(256);
+  return pl;
+}
+
+static ConvPlan plan_valu(const Geom &g) {
+  ConvPlan pl{};
   pl.variant = 0;
   pl.grid = valu_grid(g, 1);
   pl.block = dim3(256);
-  pl.lds_bytes = 0;
   pl.nblocks = grid_blocks(pl.grid);
   return pl;
+}
+
+// Whether `form` (NDC_FORM_*) with `param` can run this problem.
+static bool form_fits(const Geom &g, int dtype, int precision, int form, int param) {
+  switch (form) {
+    case NDC_FORM_VALU: return true;
+    case NDC_FORM_SMALL: return small_fits(g, dtype, precision);
+    case NDC_FORM_MFMA4:
+      return mfma_supported(g, dtype, precision) &&
+             (param == 8 || (param == 16 && precision == NDC_PREC_NATIVE));
+    case NDC_FORM_MFMA32:
+      return mfma32_fits(g, dtype, precision) && mfma_supported(g, dtype, precision) &&
+             mfma32_nt_ok(param, precision);
+    default: return false;
+  }
+}
+
+// Kernel-form overrides set by ndc_tile_override (the autotuner): exact
+// problem geometry, storage type and precision -> form and its parameter.
+struct TileOverride {
+  Geom g;
+  int dtype, precision, form, param;
+};
+static std::mutex override_mu;
+static std::vector<TileOverride> overrides;
+
+static bool same_geom(const Geom &a, const Geom &b) {
+  return a.oz == b.oz && a.oy == b.oy && a.ox == b.ox && a.iz == b.iz && a.iy == b.iy && a.ix == b.ix &&
+         a.kz == b.kz && a.ky == b.ky && a.kx == b.kx && a.offz == b.offz && a.offy == b.offy &&
+         a.offx == b.offx && a.flip == b.flip;
+}
+
+static bool find_override(const Geom &g, int dtype, int precision, int &form, int &param) {
+  std::lock_guard<std::mutex> lock(override_mu);
+  for (const TileOverride &o : overrides)
+    if (o.dtype == dtype && o.precision == precision && same_geom(o.g, g)) {
+      form = o.form;
+      param = o.param;
+      return true;
+    }
+  return false;
+}
+
+ConvPlan plan_conv(const Geom &g, int dtype, int precision) {
+  int form = 0, param = 0;
+  if (find_override(g, dtype, precision, form, param) && form_fits(g, dtype, precision, form, param)) {
+    switch (form) {
+      case NDC_FORM_SMALL: return plan_small(g, dtype);
+      case NDC_FORM_MFMA4: return plan_conv_mfma(g, dtype, precision, param);
+      case NDC_FORM_MFMA32: return plan_conv_mfma32(g, precision, param);
+      default: return plan_valu(g);
+    }
+  }
+  if (use_small(g, dtype, precision)) return plan_small(g, dtype);
+  if (mfma32_supported(g, dtype, precision) && mfma_supported(g, dtype, precision))
+    return plan_conv_mfma32(g, precision, 0);
+  if (mfma_supported(g, dtype, precision)) return plan_conv_mfma(g, dtype, precision, 0);
+  return plan_valu(g);
 }
 
 hipError_t launch_conv(const ConvPlan &pl, const Geom &g, int dtype, int precision, const void *in, const void *H,
                        void *out, const Epi &ep, hipStream_t s) {
   if (pl.variant == 1) return launch_conv_mfma(pl, g, dtype, precision, in, H, out, ep, s);
   if (pl.variant == 2) return launch_conv_small(g, dtype, in, H, out, ep, s);
-  if (pl.variant == 3) return launch_conv_mfma32(g, precision, in, H, out, ep, s);
+  if (pl.variant == 3) return launch_conv_mfma32(pl, g, precision, in, H, out, ep, s);
   return launch_conv_valu(g, dtype, precision, in, H, out, ep, 1, g.kz, s);
 }
 
@@ -200,7 +264,9 @@ const char *ndc_strerror(int status) {
   switch (status) {
     case NDC_OK: return "success";
     case NDC_EINVAL: return "invalid argument (rank, extent, half-width, count, pointer or scalar)";
-    case NDC_EUNSUPPORTED: return "valid request the library does not support (rank > 3, sizes, or bf16 with FP64)";
+    case NDC_EUNSUPPORTED:
+      return "valid request the library does not support (rank > 3, sizes, bf16 with FP64, or a kernel form that "
+             "cannot run the problem)";
     case NDC_EALIAS: return "an output buffer overlaps an input or another output";
     case NDC_ENONFINITE: return "non-finite objective";
     case NDC_EDEVICE: return "HIP runtime or kernel launch failure";
@@ -210,6 +276,46 @@ const char *ndc_strerror(int status) {
 }
 
 int ndc_version(void) { return (1 << 16) | 0; }
+
+int ndc_tile_override(int n, const int64_t *m, const int64_t *p, int dtype, int precision, int op, int form,
+                      int param) {
+  Extents E;
+  int rc = prepare(n, m, p, dtype, precision, E);
+  if (rc) return rc;
+  if (op != 0 && op != 1) return NDC_EINVAL;
+  if (form < NDC_FORM_AUTO || form > NDC_FORM_MFMA32) return NDC_EINVAL;
+  const Geom g = op == 0 ? forward_geom(E.m3, E.p3) : adjoint_geom(E.m3, E.p3);
+  if (form != NDC_FORM_AUTO && !form_fits(g, dtype, precision, form, param)) return NDC_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(override_mu);
+  for (size_t i = 0; i < overrides.size(); ++i)
+    if (overrides[i].dtype == dtype && overrides[i].precision == precision && same_geom(overrides[i].g, g)) {
+      overrides.erase(overrides.begin() + (long)i);
+      break;
+    }
+  if (form != NDC_FORM_AUTO) {
+    if (overrides.size() >= NDC_MAX_TILE_OVERRIDES) return NDC_EUNSUPPORTED;
+    overrides.push_back(TileOverride{g, dtype, precision, form, form == NDC_FORM_MFMA4 || form == NDC_FORM_MFMA32 ? param : 0});
+  }
+  return NDC_OK;
+}
+
+void ndc_tile_override_clear(void) {
+  std::lock_guard<std::mutex> lock(override_mu);
+  overrides.clear();
+}
+
+int ndc_tile_choice(int n, const int64_t *m, const int64_t *p, int dtype, int precision, int op, int *out2) {
+  Extents E;
+  int rc = prepare(n, m, p, dtype, precision, E);
+  if (rc) return rc;
+  if ((op != 0 && op != 1) || !out2) return NDC_EINVAL;
+  const Geom g = op == 0 ? forward_geom(E.m3, E.p3) : adjoint_geom(E.m3, E.p3);
+  const ConvPlan pl = plan_conv(g, dtype, precision);
+  static const int form_of[4] = {NDC_FORM_VALU, NDC_FORM_MFMA4, NDC_FORM_SMALL, NDC_FORM_MFMA32};
+  out2[0] = form_of[pl.variant];
+  out2[1] = pl.variant == 1 ? pl.xb : (pl.variant == 3 ? pl.nt : 0);
+  return NDC_OK;
+}
 
 int conv_full_nd(int n, const int64_t *m, const int64_t *p, const void *X, const void *H, void *Y, int dtype,
                  int precision, void *stream) {

@@ -58,20 +58,22 @@ hipError_t launch_kx_xb(const Geom &g, const void *in, const void *H, void *out,
 }
 
 template <int KX, int PREC>
-hipError_t launch_kx(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
+hipError_t launch_kx(int xb, const Geom &g, const void *in, const void *H, void *out, const Epi &ep,
+                     hipStream_t s) {
   if constexpr (PREC != PREC_NATIVE_) {
     return launch_kx_xb<KX, PREC, 8>(g, in, H, out, ep, s);  // bf16 forms: 32 x 32 tile only
   } else {
-    if (choose_xb(g, PREC) == 8) return launch_kx_xb<KX, PREC, 8>(g, in, H, out, ep, s);
+    if (xb == 8) return launch_kx_xb<KX, PREC, 8>(g, in, H, out, ep, s);
     return launch_kx_xb<KX, PREC, 16>(g, in, H, out, ep, s);
   }
 }
 
 template <int PREC>
-hipError_t launch_prec(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
+hipError_t launch_prec(int xb, const Geom &g, const void *in, const void *H, void *out, const Epi &ep,
+                       hipStream_t s) {
   switch (g.kx) {
 #define NDC_KX(K) \
-  case K: return launch_kx<K, PREC>(g, in, H, out, ep, s);
+  case K: return launch_kx<K, PREC>(xb, g, in, H, out, ep, s);
     NDC_KX(3) NDC_KX(5) NDC_KX(7) NDC_KX(9) NDC_KX(11) NDC_KX(13) NDC_KX(15) NDC_KX(17)
     NDC_KX(19) NDC_KX(21) NDC_KX(23) NDC_KX(25) NDC_KX(27) NDC_KX(29) NDC_KX(31) NDC_KX(33)
 #undef NDC_KX
@@ -88,10 +90,11 @@ bool mfma_supported(const Geom &g, int dtype, int) {
   return true;
 }
 
-ConvPlan plan_conv_mfma(const Geom &g, int, int precision) {
-  ConvPlan pl;
+ConvPlan plan_conv_mfma(const Geom &g, int, int precision, int xb) {
+  ConvPlan pl{};
   pl.variant = 1;
-  const dim3 t = tile_counts(g, choose_xb(g, precision));
+  pl.xb = precision != NDC_PREC_NATIVE ? 8 : (xb == 8 || xb == 16 ? xb : choose_xb(g, precision));
+  const dim3 t = tile_counts(g, pl.xb);
   pl.grid = dim3(t.x * t.y * t.z);
   pl.block = dim3(MT);
   pl.lds_bytes = 0;
@@ -99,12 +102,12 @@ ConvPlan plan_conv_mfma(const Geom &g, int, int precision) {
   return pl;
 }
 
-hipError_t launch_conv_mfma(const ConvPlan &, const Geom &g, int, int precision, const void *in, const void *H,
+hipError_t launch_conv_mfma(const ConvPlan &pl, const Geom &g, int, int precision, const void *in, const void *H,
                             void *out, const Epi &ep, hipStream_t s) {
   switch (precision) {
-    case NDC_PREC_BF16: return launch_prec<PREC_BF16_>(g, in, H, out, ep, s);
-    case NDC_PREC_SPLIT_BF16: return launch_prec<PREC_SPLIT_>(g, in, H, out, ep, s);
-    default: return launch_prec<PREC_NATIVE_>(g, in, H, out, ep, s);
+    case NDC_PREC_BF16: return launch_prec<PREC_BF16_>(8, g, in, H, out, ep, s);
+    case NDC_PREC_SPLIT_BF16: return launch_prec<PREC_SPLIT_>(8, g, in, H, out, ep, s);
+    default: return launch_prec<PREC_NATIVE_>(pl.xb, g, in, H, out, ep, s);
   }
 }
 

@@ -404,8 +404,9 @@ hipError_t launch_w(const Geom &g, const void *in, const void *H, void *out, con
 }
 
 template <int NJ, int PREC>
-hipError_t launch_nj(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
-  switch (choose_nt(g, PREC == PREC_SPLIT_ ? NDC_PREC_SPLIT_BF16 : NDC_PREC_BF16)) {
+hipError_t launch_nj(int nt, const Geom &g, const void *in, const void *H, void *out, const Epi &ep,
+                     hipStream_t s) {
+  switch (nt) {
     case 2: return launch_w<NJ, 2, PREC>(g, in, H, out, ep, s);
     case 3: return launch_w<NJ, 3, PREC>(g, in, H, out, ep, s);
     default:
@@ -415,18 +416,26 @@ hipError_t launch_nj(const Geom &g, const void *in, const void *H, void *out, co
 }
 
 template <int PREC>
-hipError_t launch_prec32(const Geom &g, const void *in, const void *H, void *out, const Epi &ep, hipStream_t s) {
-  if (g.kx + 31 <= 48) return launch_nj<3, PREC>(g, in, H, out, ep, s);
-  return launch_nj<4, PREC>(g, in, H, out, ep, s);
+hipError_t launch_prec32(int nt, const Geom &g, const void *in, const void *H, void *out, const Epi &ep,
+                         hipStream_t s) {
+  if (g.kx + 31 <= 48) return launch_nj<3, PREC>(nt, g, in, H, out, ep, s);
+  return launch_nj<4, PREC>(nt, g, in, H, out, ep, s);
 }
 
 }  // namespace
 
-bool mfma32_supported(const Geom &g, int dtype, int precision) {
+// The 32x32 tile can run this problem (PSF row width, plane size, LDS).
+bool mfma32_fits(const Geom &g, int dtype, int precision) {
   if (dtype != NDC_F32 || precision == NDC_PREC_NATIVE) return false;
   if (g.kx < WMIN_KX || g.kx > WMAX_KX || g.ky > WMAX_KY) return false;
   if ((int64_t)g.iy * g.ix >= ((int64_t)1 << 31)) return false;  // 32-bit offsets within a plane
-  if (w_lds_bytes<3>(g.ky, 1) > 160 * 1024 || w_lds_bytes<4>(g.ky, 0) > 160 * 1024) return false;
+  return w_lds_bytes<3>(g.ky, 1) <= 160 * 1024 && w_lds_bytes<4>(g.ky, 0) <= 160 * 1024;
+}
+
+bool mfma32_nt_ok(int nt, int precision) { return nt >= 2 && nt <= max_nt(precision); }
+
+bool mfma32_supported(const Geom &g, int dtype, int precision) {
+  if (!mfma32_fits(g, dtype, precision)) return false;
   // NDC_MFMA32=1 / 0 forces this form on / off wherever it is supported
   // (tests and timing); otherwise the volume decides.
   if (const char *f = getenv("NDC_MFMA32")) {
@@ -444,10 +453,11 @@ bool mfma32_supported(const Geom &g, int dtype, int precision) {
   return pad * fill >= 0.5;
 }
 
-ConvPlan plan_conv_mfma32(const Geom &g, int precision) {
-  ConvPlan pl;
+ConvPlan plan_conv_mfma32(const Geom &g, int precision, int nt) {
+  ConvPlan pl{};
   pl.variant = 3;
-  const dim3 t = w_tiles(g, choose_nt(g, precision));
+  pl.nt = mfma32_nt_ok(nt, precision) ? nt : choose_nt(g, precision);
+  const dim3 t = w_tiles(g, pl.nt);
   pl.grid = dim3(t.x * t.y * t.z);
   pl.block = dim3(WT);
   pl.lds_bytes = 0;
@@ -455,10 +465,10 @@ ConvPlan plan_conv_mfma32(const Geom &g, int precision) {
   return pl;
 }
 
-hipError_t launch_conv_mfma32(const Geom &g, int precision, const void *in, const void *H, void *out,
-                              const Epi &ep, hipStream_t s) {
-  if (precision == NDC_PREC_SPLIT_BF16) return launch_prec32<PREC_SPLIT_>(g, in, H, out, ep, s);
-  return launch_prec32<PREC_BF16_>(g, in, H, out, ep, s);
+hipError_t launch_conv_mfma32(const ConvPlan &pl, const Geom &g, int precision, const void *in, const void *H,
+                              void *out, const Epi &ep, hipStream_t s) {
+  if (precision == NDC_PREC_SPLIT_BF16) return launch_prec32<PREC_SPLIT_>(pl.nt, g, in, H, out, ep, s);
+  return launch_prec32<PREC_BF16_>(pl.nt, g, in, H, out, ep, s);
 }
 
 }  // namespace ndc

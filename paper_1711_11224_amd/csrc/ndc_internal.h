@@ -85,10 +85,12 @@ struct DState {
 
 // Launch descriptors --------------------------------------------------------
 struct ConvPlan {
-  int variant;        // 0 = VALU direct, 1 = MFMA
+  int variant;        // 0 = VALU direct, 1 = 4x4 matrix tile, 2 = small-PSF streaming, 3 = 32x32 bf16 tile
   dim3 grid, block;
   size_t lds_bytes;
   int64_t nblocks;    // number of work-groups (partial-sum slots)
+  int xb;             // variant 1: x-blocks per instruction (8 or 16)
+  int nt;             // variant 3: 32x32 blocks per wave along x (2..4)
 };
 
 // Batched form ---------------------------------------------------------------

@@ -184,3 +184,27 @@ def test_deconv_workspace_grows_with_the_laplacian_term():
     assert lib.deconv_workspace_bytes_ex(3, m, p, F32, 0, 0) == base
     # two (m+2)-extent arrays and one X-sized array at least
     assert lib.deconv_workspace_bytes_ex(3, m, p, F32, 0, 1) >= base + 4 * (2 * 10 * 11 * 12 + 8 * 9 * 10)
+
+
+def test_tile_override_checks_and_table():
+    """The kernel-form override: bad operator or form -> NDC_EINVAL, a form
+    that cannot run the problem -> NDC_EUNSUPPORTED; installed choices are
+    reported back by ndc_tile_choice and removed by NDC_FORM_AUTO / clear."""
+    m, p = I([128, 512, 512]), I([31, 15, 15])
+    out = (ctypes.c_int * 2)()
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 2, nd.NDC_FORM_MFMA4, 8) == nd.NDC_EINVAL
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, 9, 0) == nd.NDC_EINVAL
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_SMALL, 0) == nd.NDC_EUNSUPPORTED  # 63x31x31 taps
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_MFMA4, 12) == nd.NDC_EUNSUPPORTED
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_MFMA32, 3) == nd.NDC_EUNSUPPORTED  # FP32 storage, native
+    assert lib.ndc_tile_override(3, m, p, F32, nd.NDC_PREC_SPLIT_BF16, 1, nd.NDC_FORM_MFMA32, 4) == nd.NDC_EUNSUPPORTED
+    assert lib.ndc_tile_choice(3, m, p, F32, 0, 0, out) == 0 and list(out) == [nd.NDC_FORM_MFMA4, 8]
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_MFMA4, 16) == 0
+    assert lib.ndc_tile_choice(3, m, p, F32, 0, 0, out) == 0 and list(out) == [nd.NDC_FORM_MFMA4, 16]
+    assert lib.ndc_tile_choice(3, m, p, F32, 0, 1, out) == 0 and list(out) == [nd.NDC_FORM_MFMA4, 8]  # other operator
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_AUTO, 0) == 0
+    assert lib.ndc_tile_choice(3, m, p, F32, 0, 0, out) == 0 and list(out) == [nd.NDC_FORM_MFMA4, 8]
+    assert lib.ndc_tile_override(3, m, p, F32, nd.NDC_PREC_BF16, 1, nd.NDC_FORM_MFMA32, 3) == 0
+    assert lib.ndc_tile_choice(3, m, p, F32, nd.NDC_PREC_BF16, 1, out) == 0 and list(out) == [nd.NDC_FORM_MFMA32, 3]
+    lib.ndc_tile_override_clear()
+    assert lib.ndc_tile_choice(3, m, p, F32, nd.NDC_PREC_BF16, 1, out) == 0 and list(out) == [nd.NDC_FORM_MFMA32, 4]
