@@ -282,14 +282,23 @@ NDC_API int ndc_batch_deconv(ndc_batch_plan *plan, const void *const *Y, const v
  *                    (16x64, native precision only); 3 <= 2p_x+1 <= 33;
  *   NDC_FORM_MFMA32  the 32x32x16 bf16 tile (bf16 forms, 11 <= 2p_x+1 <= 33),
  *                    param = 32x32 blocks per wave along x, 2..4 (split-bf16:
- *                    2..3).
+ *                    2..3);
+ *   NDC_FORM_SLOT    the 32x32x16 row-slot tile (bf16 only; 2p_x+1 <= 32,
+ *                    2p_y+1 <= 32, 2p_z+1 <= 64 and the PSF's bf16 copy within
+ *                    the LDS budget, about 125 KiB at 63 x 31 x 31): output
+ *                    rows kept in rotating accumulator slots, so the matrix
+ *                    products are PSF taps rather than Toeplitz zeros;
+ *                    persistent, one work-group per CU.
  * NDC_EUNSUPPORTED if the form cannot run the problem (or the table, of
  * NDC_MAX_TILE_OVERRIDES entries, is full).  Every form computes the same
  * operator; results agree within the precision's rounding.  The table is
  * process-wide and guarded by a lock; a workspace sized before an override
  * changed a plan is checked again by each call.  ndc_tile_choice reports the
  * form and parameter the library would use now, as out2[0..1]. */
-enum { NDC_FORM_AUTO = 0, NDC_FORM_VALU = 1, NDC_FORM_SMALL = 2, NDC_FORM_MFMA4 = 3, NDC_FORM_MFMA32 = 4 };
+enum {
+  NDC_FORM_AUTO = 0, NDC_FORM_VALU = 1, NDC_FORM_SMALL = 2, NDC_FORM_MFMA4 = 3, NDC_FORM_MFMA32 = 4,
+  NDC_FORM_SLOT = 5
+};
 #define NDC_MAX_TILE_OVERRIDES 4096
 NDC_API int ndc_tile_override(int n, const int64_t *m, const int64_t *p, int dtype, int precision, int op,
                               int form, int param);

@@ -23,7 +23,7 @@ EXPORTS = ("conv_full_nd", "conv_adjoint_nd", "conv_dH_workspace_bytes", "conv_d
            "ndc_batch_workspace_bytes", "ndc_batch_plan_info", "ndc_batch_conv_full", "ndc_batch_conv_adjoint",
            "ndc_batch_deconv", "ndc_tile_override", "ndc_tile_override_clear", "ndc_tile_choice", "ndc_strerror",
            "ndc_version")
-NDC_FORM_AUTO, NDC_FORM_VALU, NDC_FORM_SMALL, NDC_FORM_MFMA4, NDC_FORM_MFMA32 = 0, 1, 2, 3, 4
+NDC_FORM_AUTO, NDC_FORM_VALU, NDC_FORM_SMALL, NDC_FORM_MFMA4, NDC_FORM_MFMA32, NDC_FORM_SLOT = 0, 1, 2, 3, 4, 5
 
 
 class NdcError(RuntimeError):

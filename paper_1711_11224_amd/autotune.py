@@ -97,7 +97,7 @@ def best_tuning(shapes, psf_shapes, table=None):
 
 # ---------------------------------------------------------------- single volume
 FORMS = {"valu": _native.NDC_FORM_VALU, "small": _native.NDC_FORM_SMALL, "mfma4": _native.NDC_FORM_MFMA4,
-         "mfma32": _native.NDC_FORM_MFMA32}
+         "mfma32": _native.NDC_FORM_MFMA32, "slot": _native.NDC_FORM_SLOT}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
 PRECISION_CODES = {"fp32": 0, "fp64": 0, "native": 0, "bf16": 1, "split_bf16": 2}
 OPS = ("forward", "transpose")
@@ -108,7 +108,7 @@ def conv_candidates(precision, taps):
     if PRECISION_CODES[precision] == 0:
         c = [("small", 0), ("mfma4", 8), ("mfma4", 16)]
     elif precision == "bf16":
-        c = [("mfma4", 8), ("mfma32", 2), ("mfma32", 3), ("mfma32", 4)]
+        c = [("mfma4", 8), ("mfma32", 2), ("mfma32", 3), ("mfma32", 4), ("slot", 0)]
     else:
         c = [("mfma4", 8), ("mfma32", 2), ("mfma32", 3)]
     if taps <= VALU_MAX_TAPS:

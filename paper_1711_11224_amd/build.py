@@ -22,6 +22,12 @@ CXXFLAGS = [
 ]
 
 
+# Per-file flags.  conv_slot.hip: keep the matrix instructions' accumulators in
+# ordinary VGPRs (its per-row slot clear and extraction are vector-ALU work on
+# them; in accumulation registers each would need a copy there and back).
+FILE_FLAGS = {"conv_slot.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _hipcc():
     for c in ("/opt/rocm/bin/hipcc", "hipcc"):
         if os.path.sep not in c or os.path.exists(c):
@@ -31,7 +37,7 @@ def _hipcc():
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc()] + CXXFLAGS + ["-c", src, "-o", obj]
+    cmd = [_hipcc()] + CXXFLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

@@ -33,6 +33,10 @@ bool mfma32_nt_ok(int nt, int precision);
 ConvPlan plan_conv_mfma32(const Geom &g, int precision, int nt);
 hipError_t launch_conv_mfma32(const ConvPlan &pl, const Geom &g, int precision, const void *in, const void *H,
                               void *out, const Epi &ep, hipStream_t s);
+bool slot_fits(const Geom &g, int dtype, int precision);
+ConvPlan plan_conv_slot(const Geom &g);
+hipError_t launch_conv_slot(const ConvPlan &pl, const Geom &g, const void *in, const void *H, void *out,
+                            const Epi &ep, hipStream_t s);
 bool small_supported(const Geom &g, int dtype, int precision);
 int64_t small_blocks(const Geom &g, int dtype);
 hipError_t launch_conv_small(const Geom &g, int dtype, const void *in, const void *H, void *out, const Epi &ep,
@@ -131,6 +135,7 @@ static bool form_fits(const Geom &g, int dtype, int precision, int form, int par
     case NDC_FORM_MFMA32:
       return mfma32_fits(g, dtype, precision) && mfma_supported(g, dtype, precision) &&
              mfma32_nt_ok(param, precision);
+    case NDC_FORM_SLOT: return slot_fits(g, dtype, precision);
     default: return false;
   }
 }
@@ -168,10 +173,13 @@ ConvPlan plan_conv(const Geom &g, int dtype, int precision) {
       case NDC_FORM_SMALL: return plan_small(g, dtype);
       case NDC_FORM_MFMA4: return plan_conv_mfma(g, dtype, precision, param);
       case NDC_FORM_MFMA32: return plan_conv_mfma32(g, precision, param);
+      case NDC_FORM_SLOT: return plan_conv_slot(g);
       default: return plan_valu(g);
     }
   }
   if (use_small(g, dtype, precision)) return plan_small(g, dtype);
+  if (slot_fits(g, dtype, precision) && getenv("NDC_SLOT") && getenv("NDC_SLOT")[0] == '1')
+    return plan_conv_slot(g);
   if (mfma32_supported(g, dtype, precision) && mfma_supported(g, dtype, precision))
     return plan_conv_mfma32(g, precision, 0);
   if (mfma_supported(g, dtype, precision)) return plan_conv_mfma(g, dtype, precision, 0);
@@ -183,6 +191,7 @@ hipError_t launch_conv(const ConvPlan &pl, const Geom &g, int dtype, int precisi
   if (pl.variant == 1) return launch_conv_mfma(pl, g, dtype, precision, in, H, out, ep, s);
   if (pl.variant == 2) return launch_conv_small(g, dtype, in, H, out, ep, s);
   if (pl.variant == 3) return launch_conv_mfma32(pl, g, precision, in, H, out, ep, s);
+  if (pl.variant == 4) return launch_conv_slot(pl, g, in, H, out, ep, s);
   return launch_conv_valu(g, dtype, precision, in, H, out, ep, 1, g.kz, s);
 }
 
@@ -283,7 +292,7 @@ int ndc_tile_override(int n, const int64_t *m, const int64_t *p, int dtype, int 
   int rc = prepare(n, m, p, dtype, precision, E);
   if (rc) return rc;
   if (op != 0 && op != 1) return NDC_EINVAL;
-  if (form < NDC_FORM_AUTO || form > NDC_FORM_MFMA32) return NDC_EINVAL;
+  if (form < NDC_FORM_AUTO || form > NDC_FORM_SLOT) return NDC_EINVAL;
   const Geom g = op == 0 ? forward_geom(E.m3, E.p3) : adjoint_geom(E.m3, E.p3);
   if (form != NDC_FORM_AUTO && !form_fits(g, dtype, precision, form, param)) return NDC_EUNSUPPORTED;
   std::lock_guard<std::mutex> lock(override_mu);
@@ -311,7 +320,7 @@ int ndc_tile_choice(int n, const int64_t *m, const int64_t *p, int dtype, int pr
   if ((op != 0 && op != 1) || !out2) return NDC_EINVAL;
   const Geom g = op == 0 ? forward_geom(E.m3, E.p3) : adjoint_geom(E.m3, E.p3);
   const ConvPlan pl = plan_conv(g, dtype, precision);
-  static const int form_of[4] = {NDC_FORM_VALU, NDC_FORM_MFMA4, NDC_FORM_SMALL, NDC_FORM_MFMA32};
+  static const int form_of[5] = {NDC_FORM_VALU, NDC_FORM_MFMA4, NDC_FORM_SMALL, NDC_FORM_MFMA32, NDC_FORM_SLOT};
   out2[0] = form_of[pl.variant];
   out2[1] = pl.variant == 1 ? pl.xb : (pl.variant == 3 ? pl.nt : 0);
   return NDC_OK;
