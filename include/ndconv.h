@@ -283,12 +283,14 @@ NDC_API int ndc_batch_deconv(ndc_batch_plan *plan, const void *const *Y, const v
  *   NDC_FORM_MFMA32  the 32x32x16 bf16 tile (bf16 forms, 11 <= 2p_x+1 <= 33),
  *                    param = 32x32 blocks per wave along x, 2..4 (split-bf16:
  *                    2..3);
- *   NDC_FORM_SLOT    the 32x32x16 row-slot tile (bf16 only; 2p_x+1 <= 32,
- *                    2p_y+1 <= 32, 2p_z+1 <= 64 and the PSF's bf16 copy within
- *                    the LDS budget, about 125 KiB at 63 x 31 x 31): output
- *                    rows kept in rotating accumulator slots, so the matrix
- *                    products are PSF taps rather than Toeplitz zeros;
- *                    persistent, one work-group per CU.
+ *   NDC_FORM_SLOT    the row-slot tiles (2p_x+1 <= 32, 2p_y+1 <= 32,
+ *                    2p_z+1 <= 64): output rows kept in rotating accumulator
+ *                    slots, so the matrix products are PSF taps rather than
+ *                    Toeplitz zeros; persistent, one work-group per CU.  bf16
+ *                    on the 32x32x16 instruction (the PSF's bf16 copy within
+ *                    the LDS budget, about 125 KiB at 63 x 31 x 31), FP32
+ *                    storage in native precision on the 32x32x2 FP32
+ *                    instruction.
  * NDC_EUNSUPPORTED if the form cannot run the problem (or the table, of
  * NDC_MAX_TILE_OVERRIDES entries, is full).  Every form computes the same
  * operator; results agree within the precision's rounding.  The table is

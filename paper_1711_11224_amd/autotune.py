@@ -106,7 +106,7 @@ VALU_MAX_TAPS = 729  # the general kernel is a candidate up to 9^3 taps
 
 def conv_candidates(precision, taps):
     if PRECISION_CODES[precision] == 0:
-        c = [("small", 0), ("mfma4", 8), ("mfma4", 16)]
+        c = [("small", 0), ("mfma4", 8), ("mfma4", 16), ("slot", 0)]
     elif precision == "bf16":
         c = [("mfma4", 8), ("mfma32", 2), ("mfma32", 3), ("mfma32", 4), ("slot", 0)]
     else:

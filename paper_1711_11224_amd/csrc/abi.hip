@@ -34,7 +34,12 @@ ConvPlan plan_conv_mfma32(const Geom &g, int precision, int nt);
 hipError_t launch_conv_mfma32(const ConvPlan &pl, const Geom &g, int precision, const void *in, const void *H,
                               void *out, const Epi &ep, hipStream_t s);
 bool slot_fits(const Geom &g, int dtype, int precision);
+bool slot_preferred(const Geom &g, int dtype, int precision);
 ConvPlan plan_conv_slot(const Geom &g);
+bool slot32_fits(const Geom &g, int dtype, int precision);
+ConvPlan plan_conv_slot32(const Geom &g);
+hipError_t launch_conv_slot32(const ConvPlan &pl, const Geom &g, const void *in, const void *H, void *out,
+                              const Epi &ep, hipStream_t s);
 hipError_t launch_conv_slot(const ConvPlan &pl, const Geom &g, const void *in, const void *H, void *out,
                             const Epi &ep, hipStream_t s);
 bool small_supported(const Geom &g, int dtype, int precision);
@@ -94,7 +99,8 @@ Geom adjoint_geom(const int64_t m3[3], const int64_t p3[3]) {
 static int64_t grid_blocks(dim3 g) { return (int64_t)g.x * g.y * g.z; }
 
 // Variant choice: small PSFs (every axis <= 7 taps) are bound by HBM and
-// stream through conv_small; wider ones go to the matrix cores when the x
+// stream through conv_small; large bf16 PSFs (57+ planes of 25+ x 25+ taps)
+// take the row-slot tile; other wide ones go to the matrix cores when the x
 // width fits the MFMA tile (the bf16 forms of rows 11..33 taps wide on the
 // 32x32x16 instruction, the rest on the 4x4 forms); everything else takes
 // the general VALU kernel.
@@ -135,7 +141,7 @@ static bool form_fits(const Geom &g, int dtype, int precision, int form, int par
     case NDC_FORM_MFMA32:
       return mfma32_fits(g, dtype, precision) && mfma_supported(g, dtype, precision) &&
              mfma32_nt_ok(param, precision);
-    case NDC_FORM_SLOT: return slot_fits(g, dtype, precision);
+    case NDC_FORM_SLOT: return slot_fits(g, dtype, precision) || slot32_fits(g, dtype, precision);
     default: return false;
   }
 }
@@ -173,13 +179,12 @@ ConvPlan plan_conv(const Geom &g, int dtype, int precision) {
       case NDC_FORM_SMALL: return plan_small(g, dtype);
       case NDC_FORM_MFMA4: return plan_conv_mfma(g, dtype, precision, param);
       case NDC_FORM_MFMA32: return plan_conv_mfma32(g, precision, param);
-      case NDC_FORM_SLOT: return plan_conv_slot(g);
+      case NDC_FORM_SLOT: return precision == NDC_PREC_BF16 ? plan_conv_slot(g) : plan_conv_slot32(g);
       default: return plan_valu(g);
     }
   }
   if (use_small(g, dtype, precision)) return plan_small(g, dtype);
-  if (slot_fits(g, dtype, precision) && getenv("NDC_SLOT") && getenv("NDC_SLOT")[0] == '1')
-    return plan_conv_slot(g);
+  if (slot_preferred(g, dtype, precision)) return plan_conv_slot(g);
   if (mfma32_supported(g, dtype, precision) && mfma_supported(g, dtype, precision))
     return plan_conv_mfma32(g, precision, 0);
   if (mfma_supported(g, dtype, precision)) return plan_conv_mfma(g, dtype, precision, 0);
@@ -192,6 +197,7 @@ hipError_t launch_conv(const ConvPlan &pl, const Geom &g, int dtype, int precisi
   if (pl.variant == 2) return launch_conv_small(g, dtype, in, H, out, ep, s);
   if (pl.variant == 3) return launch_conv_mfma32(pl, g, precision, in, H, out, ep, s);
   if (pl.variant == 4) return launch_conv_slot(pl, g, in, H, out, ep, s);
+  if (pl.variant == 5) return launch_conv_slot32(pl, g, in, H, out, ep, s);
   return launch_conv_valu(g, dtype, precision, in, H, out, ep, 1, g.kz, s);
 }
 
@@ -320,7 +326,8 @@ int ndc_tile_choice(int n, const int64_t *m, const int64_t *p, int dtype, int pr
   if ((op != 0 && op != 1) || !out2) return NDC_EINVAL;
   const Geom g = op == 0 ? forward_geom(E.m3, E.p3) : adjoint_geom(E.m3, E.p3);
   const ConvPlan pl = plan_conv(g, dtype, precision);
-  static const int form_of[5] = {NDC_FORM_VALU, NDC_FORM_MFMA4, NDC_FORM_SMALL, NDC_FORM_MFMA32, NDC_FORM_SLOT};
+  static const int form_of[6] = {NDC_FORM_VALU, NDC_FORM_MFMA4, NDC_FORM_SMALL, NDC_FORM_MFMA32, NDC_FORM_SLOT,
+                                 NDC_FORM_SLOT};
   out2[0] = form_of[pl.variant];
   out2[1] = pl.variant == 1 ? pl.xb : (pl.variant == 3 ? pl.nt : 0);
   return NDC_OK;

@@ -36,6 +36,7 @@
 // column shared by two work-groups costs one refill of ky - 1 rows.
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <type_traits>
 
@@ -477,6 +478,22 @@ bool slot_fits(const Geom &g, int dtype, int precision) {
   if (g.kx > SMAX_KX || g.ky > SMAX_KY || g.kz > SMAX_KZ) return false;
   const size_t lds = g.kx <= 16 ? slot_lds_bytes<1>(g.kz, g.ky) : slot_lds_bytes<2>(g.kz, g.ky);
   return lds + SW * 2 * sizeof(double) <= 160 * 1024;
+}
+
+// The built-in choice: the form wins where each input row carries much
+// matrix work (measured on MI355X, bf16: at 63 x 31 x 31 taps it takes the
+// forward of a 128 x 512 x 512 volume from 6.5 to 5.1 ms and the transpose
+// from 6.3 to 3.7 ms against the 32x32 Toeplitz tile; it ties at 31 x 15 x 15
+// and loses at 15 PSF planes or fewer, and on 2-D problems, where its fixed
+// cost per row dominates).  NDC_SLOT=1 / 0 forces it on / off where it fits.
+bool slot_preferred(const Geom &g, int dtype, int precision) {
+  if (!slot_fits(g, dtype, precision)) return false;
+  if (const char *f = getenv("NDC_SLOT")) {
+    if (f[0] == '1') return true;
+    if (f[0] == '0') return false;
+  }
+  const int64_t cols = (int64_t)((g.ox + 31) / 32) * ((g.oz + SZ - 1) / SZ);
+  return g.kz >= 57 && g.ky >= 25 && g.kx >= 25 && cols >= 128;
 }
 
 ConvPlan plan_conv_slot(const Geom &g) {

@@ -86,7 +86,7 @@ struct DState {
 // Launch descriptors --------------------------------------------------------
 struct ConvPlan {
   int variant;        // 0 = VALU direct, 1 = 4x4 matrix tile, 2 = small-PSF streaming, 3 = 32x32 bf16 tile,
-                      // 4 = 32x32 bf16 row-slot tile
+                      // 4 = 32x32 bf16 row-slot tile, 5 = 32x32 FP32 row-slot tile
   dim3 grid, block;
   size_t lds_bytes;
   int64_t nblocks;    // number of work-groups (partial-sum slots)

@@ -215,4 +215,6 @@ def test_tile_override_checks_and_table():
                                  0) == nd.NDC_EUNSUPPORTED  # 65 PSF planes
     assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_SLOT + 1, 0) == nd.NDC_EINVAL
     lib.ndc_tile_override_clear()
-    assert lib.ndc_tile_choice(3, m, p, F32, nd.NDC_PREC_BF16, 1, out) == 0 and list(out) == [nd.NDC_FORM_MFMA32, 4]
+    # the built-in rule: the row-slot tile for PSFs this large in bf16
+    assert lib.ndc_tile_choice(3, m, p, F32, nd.NDC_PREC_BF16, 1, out) == 0 and list(out) == [nd.NDC_FORM_SLOT, 0]
+    assert lib.ndc_tile_choice(3, m, p, F32, nd.NDC_PREC_SPLIT_BF16, 1, out) == 0 and list(out) == [nd.NDC_FORM_MFMA32, 2]

@@ -1,9 +1,9 @@
-"""The row-slot bf16 tile (NDC_FORM_SLOT, installed per problem through the
-override table): oracle parity on bf16-rounded operands, where only the
-FP32 summation order differs from the FP64 oracle, on shapes that reach
-every split of the PSF planes between the waves (1..8 planes per wave, in
-one and two passes), one and two 16-tap chunks, 31 of 32 row slots in use,
-columns shared between work-groups, ragged x and z tails, 1-D and 2-D
+"""The row-slot tiles (NDC_FORM_SLOT, installed per problem through the
+override table), bf16 and FP32: oracle parity (bf16 on bf16-rounded
+operands, where only the FP32 summation order differs from the FP64
+oracle) on shapes that reach every split of the PSF planes between the
+waves (1..16 planes per wave), both tap-chunk counts, 31 of 32 row slots in
+use, columns shared between work-groups, ragged x and z tails, 1-D and 2-D
 problems; run-to-run determinism; the deconvolution's and Richardson-Lucy's
 epilogues on the form; and the metric workload on sampled outputs."""
 import sys
@@ -42,15 +42,18 @@ def bf16(a):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.bfloat16).to(torch.float32).numpy()
 
 
-def install(at, m, k, form="slot"):
+def install(at, m, k, prec="bf16", form="slot"):
     for op in at.OPS:
-        at.set_form(m, k, op, form, 0, "bf16")
-        assert at.current_form(m, k, op, "bf16") == (form, 0)
+        at.set_form(m, k, op, form, 0, prec)
+        assert at.current_form(m, k, op, prec) == (form, 0)
 
 
-def clear(at, m, k):
+def clear(at, m, k, prec="bf16"):
     for op in at.OPS:
-        at.set_form(m, k, op, "auto", 0, "bf16")
+        at.set_form(m, k, op, "auto", 0, prec)
+
+
+PRECS = ["bf16", "fp32"]
 
 
 # (m, PSF extents): PSF planes per wave / passes / tap chunks noted
@@ -65,42 +68,48 @@ CASES = [((20, 40, 45), (63, 3, 5)),     # 8 per wave in two passes of 4 (edge t
          ((9, 17, 31), (1, 1, 1))]       # one tap
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("m,k", CASES)
-def test_slot_matches_oracle_on_rounded_operands(at, m, k):
+def test_slot_matches_oracle_on_rounded_operands(at, m, k, prec):
     import paper_1711_11224_amd as nd
-    say("case slot m=%s k=%s" % (m, k))
+    say("case slot m=%s k=%s %s" % (m, k, prec))
     rng = np.random.default_rng(synth.stable_seed(m, k))
     x = rng.random(m).astype(np.float32)
     h = rng.standard_normal(k).astype(np.float32)
     r = rng.standard_normal([a + b - 1 for a, b in zip(m, k)]).astype(np.float32)
-    xb, hb, rb = bf16(x), bf16(h), bf16(r)
-    install(at, m, k)
+    # operands as the kernel multiplies them
+    xb, hb, rb = (bf16(x), bf16(h), bf16(r)) if prec == "bf16" else (x, h, r)
+    install(at, m, k, prec)
     try:
         xt, ht, rt = (torch.from_numpy(v).cuda() for v in (x, h, r))
-        y = nd.conv_full_nd(xt, ht, precision="bf16")
-        g = nd.conv_adjoint_nd(rt, ht, precision="bf16")
-        y2 = nd.conv_full_nd(xt, ht, precision="bf16")
-        g2 = nd.conv_adjoint_nd(rt, ht, precision="bf16")
+        y = nd.conv_full_nd(xt, ht, precision=prec)
+        g = nd.conv_adjoint_nd(rt, ht, precision=prec)
+        y2 = nd.conv_full_nd(xt, ht, precision=prec)
+        g2 = nd.conv_adjoint_nd(rt, ht, precision=prec)
         torch.cuda.synchronize()
     finally:
-        clear(at, m, k)
+        clear(at, m, k, prec)
     assert torch.equal(y, y2) and torch.equal(g, g2)  # deterministic summation order
     y, g = y.cpu().numpy(), g.cpu().numpy()
-    # exact up to FP32 accumulation against the rounded operands ...
+    # exact up to FP32 accumulation against the operands as multiplied ...
     assert rel_l2(y, oracle.conv_full(xb, hb)) <= 1e-5
     assert rel_l2(g, oracle.conv_adjoint(rb, hb)) <= 1e-5
-    # ... and within the bf16 tolerance of the unrounded operator
-    assert rel_l2(y, oracle.conv_full(x, h)) <= 1e-2
-    assert rel_l2(g, oracle.conv_adjoint(r, h)) <= 1e-2
+    # ... and within the precision's tolerance of the unrounded operator
+    tol = 1e-2 if prec == "bf16" else 1e-5
+    assert rel_l2(y, oracle.conv_full(x, h)) <= tol
+    assert rel_l2(g, oracle.conv_adjoint(r, h)) <= tol
 
 
-def test_slot_deconvolution_and_richardson_lucy(at):
+@pytest.mark.parametrize("prec", PRECS)
+def test_slot_deconvolution_and_richardson_lucy(at, prec):
     """Five projected-gradient steps (residual, update, gradient and norm
     epilogues; Cauchy first trials) and five Richardson-Lucy steps
     (quotient and multiplicative epilogues) with the form installed, against
-    the FP64 oracle at the 5e-2 bound the bf16 deconvolution tests use."""
+    the FP64 oracle at the bound the deconvolution tests use for the
+    precision (5e-2 bf16, 1e-4 FP32)."""
     import paper_1711_11224_amd as nd
-    say("case slot deconvolution")
+    say("case slot deconvolution %s" % prec)
+    tol = 5e-2 if prec == "bf16" else 1e-4
     rng = np.random.default_rng(23)
     m, k = (10, 44, 70), (9, 11, 21)
     h = rng.random(k).astype(np.float32) + 0.1
@@ -109,50 +118,53 @@ def test_slot_deconvolution_and_richardson_lucy(at):
     y = (oracle.conv_full(xt, h) + 0.01 * rng.standard_normal([a + b - 1 for a, b in zip(m, k)])).astype(np.float32)
     x0 = np.full(m, float(xt.mean()), dtype=np.float32)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
-    install(at, m, k)
+    install(at, m, k, prec)
     try:
-        xg, st, info = nd.deconv_iterate(dev(y), dev(h), dev(x0), 5, lam=0.01, precision="bf16", rule="cauchy")
+        xg, st, info = nd.deconv_iterate(dev(y), dev(h), dev(x0), 5, lam=0.01, precision=prec, rule="cauchy")
         xr = dev(x0)
-        _, rs, rinfo = nd.rl_iterate(dev(np.maximum(y, 0)), dev(h), xr, 5, precision="bf16")
+        _, rs, rinfo = nd.rl_iterate(dev(np.maximum(y, 0)), dev(h), xr, 5, precision=prec)
         torch.cuda.synchronize()
     finally:
-        clear(at, m, k)
+        clear(at, m, k, prec)
     xo, so, done, status = oracle.deconv(y.astype(np.float64), h.astype(np.float64), x0.astype(np.float64), 5,
                                          lam=0.01, rule="cauchy")
     assert info.cpu().tolist() == [5, 0] and (done, status) == (5, 0)
     f = st.cpu().numpy()[:, 0]
     assert np.all(np.diff(f) < 0)
-    assert np.all(np.abs(f - so[:, 0]) <= 5e-2 * np.abs(so[:, 0]))
-    assert rel_l2(xg.cpu().numpy(), xo) <= 5e-2
+    assert np.all(np.abs(f - so[:, 0]) <= tol * np.abs(so[:, 0]))
+    assert rel_l2(xg.cpu().numpy(), xo) <= tol
     xro, dro = oracle.richardson_lucy(np.maximum(y, 0).astype(np.float64), h.astype(np.float64),
                                       x0.astype(np.float64), 5)
     assert rinfo.cpu().tolist()[1] == 0
-    assert rel_l2(xr.cpu().numpy(), xro) <= 5e-2
-    assert np.all(np.abs(rs.cpu().numpy() - dro) <= 5e-2 * np.abs(dro))
+    assert rel_l2(xr.cpu().numpy(), xro) <= tol
+    assert np.all(np.abs(rs.cpu().numpy() - dro) <= tol * np.abs(dro))
 
 
-def test_slot_metric_workload_sampled(at):
+@pytest.mark.parametrize("prec", PRECS)
+def test_slot_metric_workload_sampled(at, prec):
     """X 128x512x512, PSF 63x31x31 with the form installed: 2048 sampled
-    outputs of each operator against the oracle on bf16-rounded operands."""
+    outputs of each operator against the oracle (bf16: on bf16-rounded
+    operands)."""
     import paper_1711_11224_amd as nd
     cfg = synth.CONFIGS["c3_metric"]
     m, k = tuple(cfg.shape), tuple(cfg.psf_shape)
-    say("case slot metric")
+    say("case slot metric %s" % prec)
+    rnd = bf16 if prec == "bf16" else (lambda a: a)
     x = synth.make_objects(cfg).astype(np.float32)
     h = synth.psf_for(cfg).astype(np.float32)
     rng = np.random.default_rng(7)
     r = rng.standard_normal([a + b - 1 for a, b in zip(m, k)]).astype(np.float32)
     iy = rng.choice(r.size, 2048, replace=False)
     ix = rng.choice(x.size, 2048, replace=False)
-    install(at, m, k)
+    install(at, m, k, prec)
     try:
-        y = nd.conv_full_nd(torch.from_numpy(x).cuda(), torch.from_numpy(h).cuda(), precision="bf16")
+        y = nd.conv_full_nd(torch.from_numpy(x).cuda(), torch.from_numpy(h).cuda(), precision=prec)
         ys = y.view(-1)[torch.from_numpy(iy).cuda()].cpu().numpy()
         del y
-        g = nd.conv_adjoint_nd(torch.from_numpy(r).cuda(), torch.from_numpy(h).cuda(), precision="bf16")
+        g = nd.conv_adjoint_nd(torch.from_numpy(r).cuda(), torch.from_numpy(h).cuda(), precision=prec)
         gs = g.view(-1)[torch.from_numpy(ix).cuda()].cpu().numpy()
         del g
     finally:
-        clear(at, m, k)
-    assert rel_l2(ys, oracle.conv_full_at(bf16(x), bf16(h), iy)) <= 1e-5
-    assert rel_l2(gs, oracle.conv_adjoint_at(bf16(r), bf16(h), ix)) <= 1e-5
+        clear(at, m, k, prec)
+    assert rel_l2(ys, oracle.conv_full_at(rnd(x), rnd(h), iy)) <= 1e-5
+    assert rel_l2(gs, oracle.conv_adjoint_at(rnd(r), rnd(h), ix)) <= 1e-5
