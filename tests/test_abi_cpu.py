@@ -206,9 +206,13 @@ def test_tile_override_checks_and_table():
     assert lib.ndc_tile_choice(3, m, p, F32, 0, 0, out) == 0 and list(out) == [nd.NDC_FORM_MFMA4, 8]
     assert lib.ndc_tile_override(3, m, p, F32, nd.NDC_PREC_BF16, 1, nd.NDC_FORM_MFMA32, 3) == 0
     assert lib.ndc_tile_choice(3, m, p, F32, nd.NDC_PREC_BF16, 1, out) == 0 and list(out) == [nd.NDC_FORM_MFMA32, 3]
-    # the row-slot tile: bf16 only, PSF planes <= 64, rows and taps <= 32
-    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_SLOT, 0) == nd.NDC_EUNSUPPORTED
+    # the row-slot tiles: bf16 and FP32 native (not split-bf16, not FP64),
+    # PSF planes <= 64, rows and taps <= 32
+    assert lib.ndc_tile_override(3, m, p, nd.NDC_F64, 0, 0, nd.NDC_FORM_SLOT, 0) == nd.NDC_EUNSUPPORTED
     assert lib.ndc_tile_override(3, m, p, F32, nd.NDC_PREC_SPLIT_BF16, 0, nd.NDC_FORM_SLOT, 0) == nd.NDC_EUNSUPPORTED
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_SLOT, 0) == 0
+    assert lib.ndc_tile_choice(3, m, p, F32, 0, 0, out) == 0 and list(out) == [nd.NDC_FORM_SLOT, 0]
+    assert lib.ndc_tile_override(3, m, p, F32, 0, 0, nd.NDC_FORM_AUTO, 0) == 0
     assert lib.ndc_tile_override(3, m, p, F32, nd.NDC_PREC_BF16, 0, nd.NDC_FORM_SLOT, 0) == 0
     assert lib.ndc_tile_choice(3, m, p, F32, nd.NDC_PREC_BF16, 0, out) == 0 and list(out) == [nd.NDC_FORM_SLOT, 0]
     assert lib.ndc_tile_override(3, m, nd.i64_array([32, 15, 15]), F32, nd.NDC_PREC_BF16, 0, nd.NDC_FORM_SLOT,
