@@ -234,11 +234,18 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
               hstep[q] = live[q] ? S::HS : 0;
             }
             const float *src0 = tile + wrow * S::STRIDE + 4 * xb;
-            auto fetch = [&](int b, v4f(&win)[S::NW], v4f(&hv)[MG]) {
+            // M: compile-time mask of the output planes whose products are
+            // issued (all MG, or on the first and last planes of a tile's z
+            // range only the planes the input plane reaches)
+            auto fetch = [&](auto mc, int b, v4f(&win)[S::NW], v4f(&hv)[MG]) {
+              constexpr unsigned M = decltype(mc)::value;
+              static_for<0, MG>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if constexpr ((M >> q) & 1u) {
 #pragma unroll
-              for (int q = 0; q < MG; ++q)
-#pragma unroll
-                for (int c = 0; c < S::NC; ++c) hv[q][c] = hbase[q][b * hstep[q] + 16 * c];
+                  for (int c = 0; c < S::NC; ++c) hv[q][c] = hbase[q][b * hstep[q] + 16 * c];
+                }
+              });
 #pragma unroll
               for (int u = 0; u < S::KS / 4; ++u) win[u] = *(const v4f *)(src0 + b * S::STRIDE + 4 * u);
               // only the steps that exist: no load into registers left unused
@@ -252,51 +259,79 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
             v4f d[MG];
 #pragma unroll
             for (int q = 0; q < MG; ++q) d[q] = (v4f){0.f, 0.f, 0.f, 0.f};
-            auto mm = [&](const v4f(&win)[S::NW], const v4f(&hv)[MG]) {
+            auto mm = [&](auto mc, const v4f(&win)[S::NW], const v4f(&hv)[MG]) {
+              constexpr unsigned M = decltype(mc)::value;
               static_for<0, S::KS>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 const float bk = win[k >> 2][k & 3];
                 static_for<0, MG>([&](auto qc) {
                   constexpr int q = decltype(qc)::value;
-                  d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, d[q], 4, k & 15, 0);
+                  if constexpr ((M >> q) & 1u)
+                    d[q] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv[q][k >> 4], bk, d[q], 4, k & 15, 0);
                 });
               });
             };
-            // The next row's LDS reads are spread through this row's matrix
-            // instructions (two register sets, rows alternate between them).
-            constexpr int NDS = S::NW + MG * S::NC, NMM = S::KS * MG;
-            auto interleave = [&]() {
-              static_for<0, NDS>([&](auto) {
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, NMM / NDS, 0);
-              });
-              __builtin_amdgcn_sched_group_barrier(0x008, NMM, 0);
-            };
-            if constexpr (XB != 8) {
-              // one register set (the 16-block-wide tile has no registers
-              // for two): the row's reads are issued ahead of its matrix
-              // instructions
-              for (int b = b_lo; b <= b_hi; ++b) {
-                v4f win[S::NW], hv[MG];
-                fetch(b, win, hv);
-                mm(win, hv);
-                __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);
+            auto rows = [&](auto mc) {
+              constexpr unsigned M = decltype(mc)::value;
+              constexpr int NQ = __builtin_popcount(M);
+              // The next row's LDS reads are spread through this row's matrix
+              // instructions (two register sets, rows alternate between them).
+              constexpr int NDS = S::NW + NQ * S::NC, NMM = S::KS * NQ;
+              auto interleave = [&]() {
+                static_for<0, NDS>([&](auto) {
+                  __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                  __builtin_amdgcn_sched_group_barrier(0x008, NMM / NDS, 0);
+                });
                 __builtin_amdgcn_sched_group_barrier(0x008, NMM, 0);
+              };
+              if constexpr (XB != 8) {
+                // one register set (the 16-block-wide tile has no registers
+                // for two): the row's reads are issued ahead of its matrix
+                // instructions
+                for (int b = b_lo; b <= b_hi; ++b) {
+                  v4f win[S::NW], hv[MG];
+                  fetch(mc, b, win, hv);
+                  mm(mc, win, hv);
+                  __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);
+                  __builtin_amdgcn_sched_group_barrier(0x008, NMM, 0);
+                }
+              } else if (b_lo <= b_hi) {
+                v4f w0[S::NW], w1[S::NW];
+                v4f h0[MG], h1[MG];  // A operands of one row: [q][c] (NC <= 4)
+                fetch(mc, b_lo, w0, h0);
+                for (int b = b_lo;; b += 2) {
+                  fetch(mc, min(b + 1, b_hi), w1, h1);  // past the end: row b_hi again, unused
+                  mm(mc, w0, h0);
+                  interleave();
+                  if (b + 1 > b_hi) break;
+                  fetch(mc, min(b + 2, b_hi), w0, h0);
+                  mm(mc, w1, h1);
+                  interleave();
+                  if (b + 2 > b_hi) break;
+                }
               }
-            } else if (b_lo <= b_hi) {
-              v4f w0[S::NW], w1[S::NW];
-              v4f h0[MG], h1[MG];  // A operands of one row: [q][c] (NC <= 4)
-              fetch(b_lo, w0, h0);
-              for (int b = b_lo;; b += 2) {
-                fetch(min(b + 1, b_hi), w1, h1);  // past the end: row b_hi again, unused
-                mm(w0, h0);
-                interleave();
-                if (b + 1 > b_hi) break;
-                fetch(min(b + 2, b_hi), w0, h0);
-                mm(w1, h1);
-                interleave();
-                if (b + 2 > b_hi) break;
+            };
+            // The first and last MG - 1 input planes of a tile's z range reach
+            // only some of its output planes: those (a contiguous run from the
+            // first or to the last plane) issue only their own products.  Any
+            // other mask runs every plane, the unreached ones against the zero
+            // row.
+            constexpr unsigned FULL = (1u << MG) - 1u;
+            unsigned mask = 0;
+#pragma unroll
+            for (int q = 0; q < MG; ++q) mask |= (live[q] ? 1u : 0u) << q;
+            if constexpr (XB == 8 && MG == 4) {
+              switch (mask) {
+                case 0x1: rows(std::integral_constant<unsigned, 0x1>{}); break;
+                case 0x3: rows(std::integral_constant<unsigned, 0x3>{}); break;
+                case 0x7: rows(std::integral_constant<unsigned, 0x7>{}); break;
+                case 0x8: rows(std::integral_constant<unsigned, 0x8>{}); break;
+                case 0xC: rows(std::integral_constant<unsigned, 0xC>{}); break;
+                case 0xE: rows(std::integral_constant<unsigned, 0xE>{}); break;
+                default: rows(std::integral_constant<unsigned, FULL>{}); break;
               }
+            } else {
+              rows(std::integral_constant<unsigned, FULL>{});
             }
 #pragma unroll
             for (int q = 0; q < MG; ++q) acc[q] += d[q];
