@@ -22,10 +22,10 @@ CXXFLAGS = [
 ]
 
 
-# Per-file flags.  conv_slot.hip: keep the matrix instructions' accumulators in
+# Per-file flags.  The row-slot tiles (bf16 and FP32): keep the matrix instructions' accumulators in
 # ordinary VGPRs (its per-row slot clear and extraction are vector-ALU work on
 # them; in accumulation registers each would need a copy there and back).
-FILE_FLAGS = {"conv_slot.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+FILE_FLAGS = {f: ["-mllvm", "-amdgpu-mfma-vgpr-form=1"] for f in ("conv_slot.hip", "conv_slot32.hip")}
 
 
 def _hipcc():

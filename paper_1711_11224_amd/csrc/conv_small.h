@@ -87,7 +87,7 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
 
   const int yo = y0 + ly, xo = x0 + lx * SRX;
   const int64_t ostride = (int64_t)g.oy * g.ox, orow = (int64_t)yo * g.ox + xo;
-  auto emit = [&](int z, const T *acc) {  // finished output plane z
+  auto emit = [&](int z, const T *acc) __attribute__((always_inline)) {  // finished output plane z
     if (yo < g.oy) {
       const int64_t base = z * ostride + orow;
 #pragma unroll
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
     }
   };
   // input planes of output plane z: [max(0, z-offz), min(iz-1, z-offz+kz-1)]
-  auto last_in = [&](int z) { return min(g.iz - 1, z - g.offz + KZ - 1); };
+  auto last_in = [&](int z) __attribute__((always_inline)) { return min(g.iz - 1, z - g.offz + KZ - 1); };
 
   // output planes that no input plane reaches are zero
   for (int z = zlo; z < zhi; ++z)
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
   }
   const int64_t pstride = (int64_t)g.iy * g.ix;
   T inreg[SNIN];
-  auto load_plane = [&](int zin) {
+  auto load_plane = [&](int zin) __attribute__((always_inline)) {
     // uniform plane base + 32-bit per-thread offsets (always inside the
     // plane); elements outside the input are zeroed when staged, so nothing
     // waits for these loads before the plane's compute
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(ST) void conv_small_kernel(const T *__restrict__ in
 
   T done[SRX];  // finished output plane pz (-1: none) not yet stored
   int pz = -1;
-  auto stage = [&](int zin) {  // registers -> LDS buffer of plane zin
+  auto stage = [&](int zin) __attribute__((always_inline)) {  // registers -> LDS buffer of plane zin
     T *pl = planes + ((zin - r_lo) & 1) * SPLANE;
 #pragma unroll
     for (int v = 0; v < SNIN; ++v)
