@@ -145,6 +145,7 @@ constexpr int HXS = HQX + 16;        // X tile row stride (= 16 mod 64: 4 rows x
 constexpr int HGS = HQX + 4 * HMT + 4;                  // G tile row stride (>= 128 + 23 + 1)
 constexpr int HTHREADS = 256;
 __host__ __device__ constexpr int dh_tile_rows(int t) { return t >= 6 ? 32 : 16; }
+static_assert(HTHREADS == 2 * HQX, "staging: two rows of 128 columns per pass");
 
 struct DhmGeom {
   int mz, my, mx, kz, ky, kx, gy, gx;
@@ -170,13 +171,25 @@ DhmGeom dhm_geom(const int64_t m3[3], const int64_t p3[3]) {
   d.tb = (ntb + d.nbb - 1) / d.nbb;
   d.tc = (ntc + d.nbc - 1) / d.nbc;
   HQY = dh_tile_rows(d.tb > d.tc ? d.tb : d.tc);
-  // split G rows only as far as needed to give the chip ~2048 work-groups
+  // G-row splits per X plane: the count whose work-groups fill whole rounds
+  // of the resident slots (256 CUs x 2) best, costing each split's rounds
+  // by its tiles plus a quarter tile of per-work-group overhead (X halo,
+  // reduction); fewer splits on ties
   const int64_t base = (int64_t)d.kz * d.nbb * d.nbc * d.mz;
   const int ytiles = (d.gy + HQY - 1) / HQY;
-  int64_t want = (2048 + base - 1) / base;
-  if (want > ytiles) want = ytiles;
-  if (want < 1) want = 1;
-  const int per = (int)((ytiles + want - 1) / want);
+  constexpr int64_t slots = 512;
+  int per = ytiles;
+  double best = -1.0;
+  for (int n = 1; n <= ytiles && n <= 32; ++n) {
+    const int pn = (ytiles + n - 1) / n;
+    const int nys = (ytiles + pn - 1) / pn;
+    const int64_t rounds = (base * nys + slots - 1) / slots;
+    const double cost = (double)rounds * (pn + 0.25);
+    if (best < 0.0 || cost < best * 0.999) {
+      best = cost;
+      per = pn;
+    }
+  }
   d.ysplit = per * HQY;
   d.nys = (d.gy + d.ysplit - 1) / d.ysplit;
   d.nsplit = d.mz * d.nys;
@@ -217,6 +230,7 @@ __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__res
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int k = lane >> 2, q4 = lane & 3;               // block (x offset), i or j
+  const int cx = tid & (HQX - 1), rp = tid / HQX;       // staging column and row parity
   const float *Xp = X + (int64_t)z * d.my * d.mx;
   const float *Gp = G + (int64_t)(z + a) * d.gy * d.gx;
 
@@ -229,19 +243,51 @@ __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__res
   const int y_lo = ys * d.ysplit, y_hi = min(d.gy, y_lo + d.ysplit);
   for (int yt = y_lo; yt < y_hi; yt += HQY) {
     for (int xt0 = 0; xt0 < d.mx; xt0 += HQX) {
-      __syncthreads();  // previous tile no longer read
-      // X rows yt - b0 - 4T + 1 .. yt + 15 - b0, columns xt0 .. xt0 + 127
+      // Staging: every load of the tile is issued first, unconditionally, at
+      // offsets clamped into the plane, and the LDS writes zero what lies
+      // outside; the loads are then in flight together instead of one
+      // memory latency each.  Thread columns: cx (and cx + 128 .. for G's
+      // last HGS - 128 columns), rows of the same parity rp.
+      constexpr int NXU = (xrows + 1) / 2;                          // X rows per thread
+      constexpr int NGU = HQY / 2;                                  // G rows per thread, first 128 columns
+      constexpr int GEX = HGS - HQX;                                // G columns past 128
+      constexpr int NGE = (HQY * GEX + HTHREADS - 1) / HTHREADS;    // those per thread
+      // X rows yt - b0 - 4T + 1 .. yt + HQY - 1 - b0, columns xt0 .. xt0 + 127
       const int xr0 = yt - b0 - 4 * T + 1;
-      for (int e = tid; e < xrows * HQX; e += HTHREADS) {
-        const int r = e / HQX, c = e - r * HQX;
-        const int yx = xr0 + r, xx = xt0 + c;
-        xt[r * HXS + c] = (yx >= 0 && yx < d.my && xx < d.mx) ? Xp[(int64_t)yx * d.mx + xx] : 0.f;
+      const int xx = xt0 + cx, xxc = min(xx, d.mx - 1);
+      const int xg = xt0 + c0 + cx, xgc = min(xg, d.gx - 1);
+      float xv[NXU], gv[NGU], ge[NGE];
+#pragma unroll
+      for (int u = 0; u < NXU; ++u) {
+        const int yc = min(max(xr0 + 2 * u + rp, 0), d.my - 1);
+        xv[u] = Xp[(unsigned)(yc * d.mx + xxc)];
       }
-      // G rows yt .. yt + 15, columns xt0 + c0 .. xt0 + c0 + HGS - 1
-      for (int e = tid; e < HQY * HGS; e += HTHREADS) {
-        const int r = e / HGS, c = e - r * HGS;
-        const int yg = yt + r, xg = xt0 + c0 + c;
-        gt[e] = (yg < y_hi && xg < d.gx) ? Gp[(int64_t)yg * d.gx + xg] : 0.f;
+#pragma unroll
+      for (int u = 0; u < NGU; ++u) {
+        const int yc = min(yt + 2 * u + rp, d.gy - 1);
+        gv[u] = Gp[(unsigned)(yc * d.gx + xgc)];
+      }
+#pragma unroll
+      for (int v = 0; v < NGE; ++v) {
+        const int e = tid + HTHREADS * v, r = min(e / GEX, HQY - 1), c = HQX + e % GEX;
+        const int yc = min(yt + r, d.gy - 1), xc = min(xt0 + c0 + c, d.gx - 1);
+        ge[v] = Gp[(unsigned)(yc * d.gx + xc)];
+      }
+      __syncthreads();  // previous tile no longer read
+#pragma unroll
+      for (int u = 0; u < NXU; ++u) {
+        const int r = 2 * u + rp, yx = xr0 + r;
+        if (r < xrows) xt[r * HXS + cx] = (yx >= 0 && yx < d.my && xx < d.mx) ? xv[u] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < NGU; ++u) {
+        const int r = 2 * u + rp;
+        gt[r * HGS + cx] = (yt + r < y_hi && xg < d.gx) ? gv[u] : 0.f;
+      }
+#pragma unroll
+      for (int v = 0; v < NGE; ++v) {
+        const int e = tid + HTHREADS * v, r = e / GEX, c = HQX + e % GEX;
+        if (r < HQY) gt[r * HGS + c] = (yt + r < y_hi && xt0 + c0 + c < d.gx) ? ge[v] : 0.f;
       }
       __syncthreads();
       const int nch = min(HQX, d.mx - xt0 + 15) / 16;  // 16-wide chunks with any X column
@@ -308,7 +354,8 @@ __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__res
 }  // namespace
 
 bool dh_supported(const int64_t m3[3], const int64_t p3[3], int dtype) {
-  if (dtype == NDC_F32) return true;  // matrix-core form: any PSF (blocks of 24 x 24)
+  if (dtype == NDC_F32)  // matrix-core form: any PSF (blocks of 24 x 24); 32-bit offsets inside a plane
+    return m3[1] * m3[2] < ((int64_t)1 << 31) && (m3[1] + 2 * p3[1]) * (m3[2] + 2 * p3[2]) < ((int64_t)1 << 31);
   const DhGeom d = dh_geom(m3, p3);
   return d.ky * d.ncg <= 256 && dh_lds_bytes(d, 8) <= 96 * 1024;
 }
