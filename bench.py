@@ -494,8 +494,10 @@ def bench_paper_2d(nd, torch, iters=100):
 
 def bench_small_psf(nd, torch, reps=5):
     """Small-PSF sweep on the metric volume (128x512x512), Gaussian PSFs 3^3,
-    5^3, 7^3: HBM-bound operators, reported as algorithmic GB/s (4 (N + N_Y)
-    bytes per operator: read one side, write the other) against 8 TB/s."""
+    5^3, 7^3, reported as algorithmic GB/s (4 (N + N_Y) bytes per operator:
+    read one side, write the other) against 8 TB/s, and as 2 N K FLOP per
+    operator against the 157.3 TFLOP/s FP32 vector peak; `bound` names the
+    larger of the two floors (HBM at 3^3, the vector ALUs from 5^3 on)."""
     import synth
     m = synth.CONFIGS["c3_metric"].shape
     g = torch.Generator(device="cuda").manual_seed(5)
@@ -514,7 +516,9 @@ def bench_small_psf(nd, torch, reps=5):
                            "transpose_hbm_frac": round(by / (adj * 1e-3) / 8e12, 3),
                            # the slower operator bounds a step, as in the main roofline
                            "hbm_frac": round(by / (max(fwd, adj) * 1e-3) / 8e12, 3),
-                           "gmacs": round(2.0 * N * k ** 3 / ((fwd + adj) * 1e-3) / 1e9, 1)}
+                           "gmacs": round(2.0 * N * k ** 3 / ((fwd + adj) * 1e-3) / 1e9, 1),
+                           "bound": "hbm" if by / 8e12 >= 2.0 * N * k ** 3 / 157.3e12 else "alu",
+                           "alu_frac": round(2.0 * N * k ** 3 / 157.3e12 / (max(fwd, adj) * 1e-3), 3)}
     return out
 
 
