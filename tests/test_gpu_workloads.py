@@ -149,7 +149,7 @@ def c3_deconv_inputs(nd):
     x0 = synth.flat_start(y, h, cfg.shape).astype(np.float32)
     ax0 = oracle.conv_full_separable(np.full(cfg.shape, float(x0.ravel()[0])), factors)
     f0 = 0.5 * float(np.sum((ax0 - y.astype(np.float64)) ** 2))
-    return cfg, h, y, x0, f0
+    return cfg, h, y, x0, f0, ax0
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "split_bf16"])
@@ -157,7 +157,7 @@ def test_c3_deconv_steps_properties(nd, c3_deconv_inputs, prec):
     """Metric workload, a few steps in each precision: every step accepted,
     f strictly decreasing, X >= 0, and f(X^0) against the oracle (flat X^0
     with the separable Gaussian PSF, one 1-D full convolution per axis)."""
-    cfg, h, y, x0, f0 = c3_deconv_inputs
+    cfg, h, y, x0, f0, _ = c3_deconv_inputs
     say("case c3 deconv %s" % prec)
     xg, st, info = nd.deconv_iterate(torch.from_numpy(y).cuda(), torch.from_numpy(h).cuda(),
                                      torch.from_numpy(x0).cuda(), 3, precision=prec)
@@ -167,6 +167,41 @@ def test_c3_deconv_steps_properties(nd, c3_deconv_inputs, prec):
     assert np.all(np.diff(f) < 0)
     assert float(xg.min()) >= 0.0
     assert abs(f[0] - f0) <= F0_TOL[prec] * f0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "split_bf16"])
+def test_c3_first_step_sampled_x_vs_oracle(nd, c3_deconv_inputs, prec):
+    """Metric workload, one projected-gradient step (Step 2) from the flat
+    start in each precision, against the oracle on 2048 sampled voxels:
+    the first trial is the fixed rule's delta_0 = 1 / ||H||_1^2 and is
+    accepted (f decreases for any delta <= 1/L); X_1 = max(X_0 - delta_0
+    A^T (A X_0 - Y), 0) with the oracle's residual of the flat start (one
+    1-D full convolution per axis) and its transpose evaluated at each
+    sampled voxel.  Tolerance: the operator's relative error e reaches the
+    gradient through R (amplified by ||A X_0|| / ||R||) and directly, and
+    X_1 through delta_0 ||g|| / ||X_1|| (both measured on the oracle's
+    side), so amp * (ratio + 1) * e, with e = 1e-5 / 1e-2 / 1e-4."""
+    cfg, h, y, x0, f0, ax0 = c3_deconv_inputs
+    say("case c3 first step sampled X %s" % prec)
+    xg, st, info = nd.deconv_iterate(torch.from_numpy(y).cuda(), torch.from_numpy(h).cuda(),
+                                     torch.from_numpy(x0).cuda(), 1, precision=prec)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [1, 0]
+    st = st.cpu().numpy()
+    h64 = h.astype(np.float64)
+    d0 = oracle.initial_delta(h64)
+    assert st[1, 2] == 0 and abs(st[1, 1] - d0) <= 1e-12 * d0
+    r = ax0 - y.astype(np.float64)
+    idx = np.random.default_rng(17).choice(x0.size, 2048, replace=False)
+    g = oracle.conv_adjoint_at(r, h64, idx)
+    x1 = np.maximum(x0.astype(np.float64).ravel()[idx] - d0 * g, 0.0)
+    amp = d0 * np.linalg.norm(g) / np.linalg.norm(x1)
+    ratio = float(np.linalg.norm(ax0) / np.linalg.norm(r))
+    e = {"fp32": 1e-5, "bf16": 1e-2, "split_bf16": 1e-4}[prec]
+    got = xg.view(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    err = rel_l2(got, x1)
+    say("  rel L2 %.2e (tolerance %.2e; amp %.2f, ratio %.2f)" % (err, amp * (ratio + 1) * e, amp, ratio))
+    assert err <= amp * (ratio + 1) * e
 
 
 # ---- the paper's two 2-D experiment shapes (synthetic stand-ins) ----------
