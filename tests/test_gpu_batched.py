@@ -240,6 +240,32 @@ def test_batched_workload_64_volumes(nd):
     plan.close()
 
 
+def test_batched_workload_64_volumes_operators_sampled(nd):
+    """The batched workload's operators (64 volumes, 32^3 .. 96x160x160,
+    PSFs 9..31 per axis, the tuning the bench uses) against the oracle on
+    256 sampled outputs of each operator in every volume, plus each
+    volume's eight corner outputs (where the fewest taps are in range)."""
+    cfgs = synth.batched_configs(64)
+    say("case c4 batched 64 operators sampled")
+    rng = np.random.default_rng(64)
+    xs = [rng.random(c.shape).astype(np.float32) for c in cfgs]
+    hs = [synth.gaussian_psf(c.psf_shape, c.sigmas).astype(np.float32) for c in cfgs]
+    rs = [rng.standard_normal([a + b - 1 for a, b in zip(c.shape, c.psf_shape)]).astype(np.float32) for c in cfgs]
+    plan = nd.batched.BatchPlan([c.shape for c in cfgs], [c.psf_shape for c in cfgs], tuning=(4, 2, 2, 1))
+    gh = [torch.from_numpy(h).cuda() for h in hs]
+    ys = plan.conv_full([torch.from_numpy(x).cuda() for x in xs], gh)
+    gs = plan.conv_adjoint([torch.from_numpy(r).cuda() for r in rs], gh)
+    torch.cuda.synchronize()
+    for v, c in enumerate(cfgs):
+        y, g = ys[v].cpu().numpy(), gs[v].cpu().numpy()
+        for out, shape, fn, src in ((y, y.shape, oracle.conv_full_at, xs[v]), (g, g.shape, oracle.conv_adjoint_at, rs[v])):
+            corners = np.ravel_multi_index(np.array(np.meshgrid(*[[0, e - 1] for e in shape], indexing="ij")).reshape(3, -1),
+                                           shape)
+            idx = np.concatenate([rng.choice(out.size, 256, replace=False), corners])
+            assert rel_l2(out.ravel()[idx], fn(src, hs[v].astype(np.float64), idx)) <= 1e-5, (v, c.shape, c.psf_shape)
+    plan.close()
+
+
 def test_autotuner_table(nd, tmp_path):
     from paper_1711_11224_amd import autotune
     say("case autotune")

@@ -100,6 +100,18 @@ def test_c3_forward_edges_exact_subvolume(nd, c3):
     assert rel_l2(y.ravel()[idx], oracle.conv_full_at(x, h, idx)) <= 1e-5
 
 
+def test_c3_transpose_edges_exact_subvolume(nd, c3):
+    """A corner sub-volume of the metric transpose (the first and last
+    planes, rows and columns of X, where the PSF reaches past Y's zero
+    padding) against the oracle evaluated at each of its voxels."""
+    cfg, x, h, r, *_ = c3
+    say("case c3 transpose corner")
+    g = nd.conv_adjoint_nd(torch.from_numpy(r).cuda(), torch.from_numpy(h).cuda()).cpu().numpy()
+    zz, yy, xx = np.meshgrid(np.r_[0:3, 125:128], np.r_[0:3, 509:512], np.r_[0:5, 507:512], indexing="ij")
+    idx = np.ravel_multi_index((zz.ravel(), yy.ravel(), xx.ravel()), g.shape)
+    assert rel_l2(g.ravel()[idx], oracle.conv_adjoint_at(r, h, idx)) <= 1e-5
+
+
 def _c2_inputs():
     sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
     import make_c2_trajectory as mk
