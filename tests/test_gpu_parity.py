@@ -158,10 +158,15 @@ def test_deconv_reduced_precision_wide_rows(nd, prec, tol, rule, mu, monkeypatch
 
 
 # dH cases: one and several 128-column / 16-row tiles with ragged tails, PSF
-# rows or columns spanning several 24-wide blocks, 1x1x1 PSF, 1-D and 2-D
+# rows or columns spanning several 24-wide blocks, 1x1x1 PSF, 1-D and 2-D,
+# and the broadcast form
 DH_CASES = [((6, 9, 11), (1, 2, 3)), ((16, 40, 40), (3, 2, 4)), ((20, 33), (2, 5)),
             ((4, 50, 300), (1, 13, 2)), ((3, 70, 140), (2, 3, 14)), ((2, 20, 130), (0, 0, 0)),
-            ((300,), (7,)), ((5, 37, 29), (2, 10, 10))]
+            ((300,), (7,)), ((5, 37, 29), (2, 10, 10)),
+            # broadcast form (21- and 25-row PSF planes): scalar and 16-byte
+            # staging, fewer X planes than PSF planes, ragged x tiles
+            ((9, 37, 70), (4, 10, 10)), ((12, 40, 64), (15, 10, 10)), ((7, 150, 136), (3, 12, 12)),
+            ((5, 33, 257), (2, 10, 11))]
 
 
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
