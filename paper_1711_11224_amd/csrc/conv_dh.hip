@@ -516,13 +516,30 @@ __global__ __launch_bounds__(HTHREADS, 2) void dh_bcast_kernel(const float *__re
   const int cx = tid & (BQX - 1), rp = tid / BQX;  // staging column and row parity
   const int nxr = nag * d.pr;                      // X rows staged per tile (all planes)
   const bool x_vec = (d.mx & 3) == 0 && ((uintptr_t)X & 15) == 0;  // 16-byte X loads
+  const bool g_vec = (d.gx & 3) == 0 && ((uintptr_t)G & 15) == 0;  // 16-byte G loads
   for (int yt = y_lo; yt < y_hi; yt += HQY) {
     for (int xt0 = 0; xt0 < d.mx; xt0 += BQX) {
       __syncthreads();  // previous tile no longer read
       // G rows yt .. yt + HQY - 1, columns xt0 + c0 + [0, BGS): loads first
       // (unconditional, at clamped offsets), then the LDS writes with what
-      // lies outside G zeroed
-      {
+      // lies outside G zeroed; 16-byte loads where G's rows allow them
+      if (g_vec) {
+        constexpr int G4 = BGS / 4, NG4 = (HQY * G4 + HTHREADS - 1) / HTHREADS;
+        float4 gv4[NG4];
+#pragma unroll
+        for (int v = 0; v < NG4; ++v) {
+          const int e = tid + HTHREADS * v, r = min(e / G4, HQY - 1), c = (e % G4) * 4;
+          gv4[v] = *(const float4 *)(Gp + (unsigned)(min(yt + r, d.gy - 1) * d.gx + min(xt0 + c0 + c, d.gx - 4)));
+        }
+#pragma unroll
+        for (int v = 0; v < NG4; ++v) {
+          const int e = tid + HTHREADS * v, r = e / G4, c = (e % G4) * 4;
+          if (e < HQY * G4) {
+            const bool ok = yt + r < y_hi && xt0 + c0 + c < d.gx;
+            *(float4 *)(gt + r * BGS + c) = ok ? gv4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+        }
+      } else {
         constexpr int NGU = HQY / 2, NGE = HQY * (BGS - BQX) / HTHREADS;
         float gv[NGU], ge[NGE];
         const int xg = xt0 + c0 + cx, xgc = min(xg, d.gx - 1);
