@@ -211,7 +211,7 @@ __device__ __forceinline__ void dh_sfor(F &&f) {
 
 // T x T tiles per wave (T = the larger of the block's tile counts; tiles past
 // the block are computed and dropped).
-template <int T>
+template <int T, bool XV>
 __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__restrict__ X, const float *__restrict__ G,
                                                               float *__restrict__ part, DhmGeom d) {
   constexpr int HQY = dh_tile_rows(T);             // G rows per staged tile (HQY / 4 per wave)
@@ -259,11 +259,25 @@ __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__res
       const int xr0 = yt - b0 - 4 * T + 1;
       const int xx = xt0 + cx, xxc = min(xx, d.mx - 1);
       const int xg = xt0 + c0 + cx, xgc = min(xg, d.gx - 1);
-      float xv[NXU], gv[NGU], ge[NGE];
+      // XV: 16-byte X loads (X's rows a multiple of 4 floats, X aligned):
+      // thread columns c4, c4 + 1 .. c4 + 3, rows of the same residue mod 8
+      constexpr int NX4 = (xrows + 7) / 8;
+      const int c4 = (tid & 31) * 4, r8 = tid >> 5;
+      const int x4 = xt0 + c4, x4c = min(x4, d.mx - 4);
+      float xv[XV ? 1 : NXU], gv[NGU], ge[NGE];
+      float4 xv4[XV ? NX4 : 1];
+      if constexpr (XV) {
 #pragma unroll
-      for (int u = 0; u < NXU; ++u) {
-        const int yc = min(max(xr0 + 2 * u + rp, 0), d.my - 1);
-        xv[u] = Xp[(unsigned)(yc * d.mx + xxc)];
+        for (int u = 0; u < NX4; ++u) {
+          const int yc = min(max(xr0 + 8 * u + r8, 0), d.my - 1);
+          xv4[u] = *(const float4 *)(Xp + (unsigned)(yc * d.mx + x4c));
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < NXU; ++u) {
+          const int yc = min(max(xr0 + 2 * u + rp, 0), d.my - 1);
+          xv[u] = Xp[(unsigned)(yc * d.mx + xxc)];
+        }
       }
 #pragma unroll
       for (int u = 0; u < NGU; ++u) {
@@ -277,10 +291,19 @@ __global__ __launch_bounds__(HTHREADS, 2) void dh_mfma_kernel(const float *__res
         ge[v] = Gp[(unsigned)(yc * d.gx + xc)];
       }
       __syncthreads();  // previous tile no longer read
+      if constexpr (XV) {
 #pragma unroll
-      for (int u = 0; u < NXU; ++u) {
-        const int r = 2 * u + rp, yx = xr0 + r;
-        if (r < xrows) xt[r * HXS + cx] = (yx >= 0 && yx < d.my && xx < d.mx) ? xv[u] : 0.f;
+        for (int u = 0; u < NX4; ++u) {
+          const int r = 8 * u + r8, yx = xr0 + r;
+          if (r < xrows)
+            *(float4 *)(xt + r * HXS + c4) = (yx >= 0 && yx < d.my && x4 < d.mx) ? xv4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < NXU; ++u) {
+          const int r = 2 * u + rp, yx = xr0 + r;
+          if (r < xrows) xt[r * HXS + cx] = (yx >= 0 && yx < d.my && xx < d.mx) ? xv[u] : 0.f;
+        }
       }
 #pragma unroll
       for (int u = 0; u < NGU; ++u) {
@@ -774,10 +797,16 @@ hipError_t launch_dh(const int64_t m3[3], const int64_t p3[3], int dtype, const 
     const DhmGeom d = dhm_geom(m3, p3);
     const int64_t blocks = (int64_t)d.kz * d.nbb * d.nbc * d.nsplit;
     const dim3 grid((unsigned)blocks), block(HTHREADS);
+    const bool xv = (d.mx & 3) == 0 && ((uintptr_t)X & 15) == 0;  // 16-byte X staging
     switch (max(d.tb, d.tc)) {
 #define NDC_DHM(T)                                                                                            \
   case T:                                                                                                      \
-    hipLaunchKernelGGL(dh_mfma_kernel<T>, grid, block, 0, s, (const float *)X, (const float *)G, (float *)ws, d); \
+    if (xv)                                                                                                    \
+      hipLaunchKernelGGL((dh_mfma_kernel<T, true>), grid, block, 0, s, (const float *)X, (const float *)G,     \
+                         (float *)ws, d);                                                                      \
+    else                                                                                                       \
+      hipLaunchKernelGGL((dh_mfma_kernel<T, false>), grid, block, 0, s, (const float *)X, (const float *)G,    \
+                         (float *)ws, d);                                                                      \
     break;
       NDC_DHM(1) NDC_DHM(2) NDC_DHM(3) NDC_DHM(4) NDC_DHM(5) NDC_DHM(6)
 #undef NDC_DHM
