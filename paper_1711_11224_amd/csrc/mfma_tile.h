@@ -130,58 +130,71 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
   const int r_hi = min(g.iz - 1, z0 + MG - 1 + g.kz - 1 - g.offz);
 
   // staging helpers ------------------------------------------------------------
+  // The staging loads are unconditional, from offsets clamped into the
+  // input (and the PSF), with a bit per element for what lies outside; the
+  // zeros are applied at the LDS stores, and an empty asm keeps each loaded
+  // value's first use there.  A conditional load lets the compiler merge its
+  // value right after it, which waits for the load before the plane's
+  // matrix instructions instead of after them.
+  static_assert(S::NIN <= 32 && S::NH <= 32, "one mask bit per staged element");
   float inreg[S::NIN];
   float hreg[S::NH];
+  unsigned inok = 0, hok = 0;
   auto load_plane = [&](int zin) {
+    const float *plane = in + (int64_t)zin * g.iy * g.ix;
+    inok = 0;
 #pragma unroll
     for (int u = 0; u < S::NIN; ++u) {
       const int e = tid + u * MT;
       const int r = e / S::TCOLS, q = e - r * S::TCOLS;
       const int yin = y0 + r - g.offy, xin = x0 + q - g.offx;
-      float v = 0.f;
-      if (r < rows && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix)
-        v = in[((int64_t)zin * g.iy + yin) * g.ix + xin];
-      inreg[u] = v;
+      const bool ok = r < rows && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix;
+      const int yc = min(max(yin, 0), g.iy - 1), xc = min(max(xin, 0), g.ix - 1);
+      inreg[u] = plane[(unsigned)(yc * g.ix + xc)];
+      inok |= (ok ? 1u : 0u) << u;
     }
   };
   auto store_plane = [&](float *t) {
 #pragma unroll
     for (int u = 0; u < S::NIN; ++u) {
+      asm volatile("" : "+v"(inreg[u]));  // keep the load's use here
       const int e = tid + u * MT;
       const int r = e / S::TCOLS, q = e - r * S::TCOLS;
+      const float v = ((inok >> u) & 1u) ? inreg[u] : 0.f;
       if (r < rows) {
         if constexpr (PREC == PREC_NATIVE_) {
-          t[r * S::STRIDE + q] = inreg[u];
+          t[r * S::STRIDE + q] = v;
         } else {  // rounded once here instead of once per PSF row
           __bf16 *tb = (__bf16 *)t;
-          const __bf16 hi = (__bf16)inreg[u];
+          const __bf16 hi = (__bf16)v;
           tb[r * S::STRIDE_B + q] = hi;
-          if constexpr (PREC == PREC_SPLIT_) tb[lo_off + r * S::STRIDE_B + q] = (__bf16)(inreg[u] - (float)hi);
+          if constexpr (PREC == PREC_SPLIT_) tb[lo_off + r * S::STRIDE_B + q] = (__bf16)(v - (float)hi);
         }
       }
     }
   };
   auto load_h = [&](int a) {  // PSF plane a of Hc, rows padded with 3 leading zeros
+    const int ha = g.flip ? g.kz - 1 - a : a;
+    hok = 0;
 #pragma unroll
     for (int u = 0; u < S::NH; ++u) {
       const int e = tid + u * MT;
       const int b = e / S::HS, t = e - b * S::HS - 3;
-      float v = 0.f;
-      if (b < g.ky && t >= 0 && t < KX) {
-        const int ha = g.flip ? g.kz - 1 - a : a;
-        const int hb = g.flip ? g.ky - 1 - b : b;
-        const int hc = g.flip ? KX - 1 - t : t;
-        v = H[((int64_t)ha * g.ky + hb) * KX + hc];
-      }
-      hreg[u] = v;
+      const bool ok = b < g.ky && t >= 0 && t < KX;
+      const int bc = min(b, g.ky - 1), tcl = min(max(t, 0), KX - 1);
+      const int hb = g.flip ? g.ky - 1 - bc : bc;
+      const int hc = g.flip ? KX - 1 - tcl : tcl;
+      hreg[u] = H[((int64_t)ha * g.ky + hb) * KX + hc];
+      hok |= (ok ? 1u : 0u) << u;
     }
   };
   auto store_h = [&](int a) {
     float *dst = ring + (a % (MG + 1)) * hplane;
 #pragma unroll
     for (int u = 0; u < S::NH; ++u) {
+      asm volatile("" : "+v"(hreg[u]));  // keep the load's use here
       const int e = tid + u * MT;
-      if (e < hplane) dst[e] = hreg[u];
+      if (e < hplane) dst[e] = ((hok >> u) & 1u) ? hreg[u] : 0.f;
     }
   };
 
@@ -435,6 +448,10 @@ __device__ __forceinline__ void mfma_tile(const float *__restrict__ in, const fl
         }
       }
 
+      // The next plane's stores stay after this plane's matrix instructions:
+      // they target the other buffer, so the compiler may otherwise move them
+      // up to the loads and wait for the loads there.
+      asm volatile("" ::: "memory");
       if (more) store_plane(((zin + 1 - r_lo) & 1) ? tile1 : tile0);
       if (new_h) store_h(a_new);
       __syncthreads();
