@@ -529,47 +529,54 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
 
   float inreg[RT_NIN];
   float hreg[RT_NH];
+  // Unconditional staging loads with a mask, as in mfma_tile.
+  static_assert(RT_NIN <= 32 && RT_NH <= 32, "one mask bit per staged element");
+  unsigned inok = 0, hok = 0;
   auto load_plane = [&](int zin) {
+    const float *plane = in + (int64_t)zin * g.iy * g.ix;
+    inok = 0;
 #pragma unroll
     for (int u = 0; u < RT_NIN; ++u) {
       const int e = tid + u * MT;
       const int r = e / S.tcols, q = e - r * S.tcols;
       const int yin = y0 + r - g.offy, xin = x0 + q - g.offx;
-      float v = 0.f;
-      if (r < rows && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix)
-        v = in[((int64_t)zin * g.iy + yin) * g.ix + xin];
-      inreg[u] = v;
+      const bool ok = r < rows && yin >= 0 && yin < g.iy && xin >= 0 && xin < g.ix;
+      const int yc = min(max(yin, 0), g.iy - 1), xc = min(max(xin, 0), g.ix - 1);
+      inreg[u] = plane[(unsigned)(yc * g.ix + xc)];
+      inok |= (ok ? 1u : 0u) << u;
     }
   };
   auto store_plane = [&](float *t) {
 #pragma unroll
     for (int u = 0; u < RT_NIN; ++u) {
+      asm volatile("" : "+v"(inreg[u]));  // keep the load's use here
       const int e = tid + u * MT;
       const int r = e / S.tcols, q = e - r * S.tcols;
-      if (r < rows) t[r * S.stride + q] = inreg[u];
+      if (r < rows) t[r * S.stride + q] = ((inok >> u) & 1u) ? inreg[u] : 0.f;
     }
   };
   auto load_h = [&](int a) {
+    const int ha = g.flip ? g.kz - 1 - a : a;
+    hok = 0;
 #pragma unroll
     for (int u = 0; u < RT_NH; ++u) {
       const int e = tid + u * MT;
       const int b = e / S.hs, t = e - b * S.hs - 3;
-      float v = 0.f;
-      if (b < g.ky && t >= 0 && t < g.kx) {
-        const int ha = g.flip ? g.kz - 1 - a : a;
-        const int hb = g.flip ? g.ky - 1 - b : b;
-        const int hc = g.flip ? g.kx - 1 - t : t;
-        v = H[((int64_t)ha * g.ky + hb) * g.kx + hc];
-      }
-      hreg[u] = v;
+      const bool ok = b < g.ky && t >= 0 && t < g.kx;
+      const int bc = min(b, g.ky - 1), tcl = min(max(t, 0), g.kx - 1);
+      const int hb = g.flip ? g.ky - 1 - bc : bc;
+      const int hc = g.flip ? g.kx - 1 - tcl : tcl;
+      hreg[u] = H[((int64_t)ha * g.ky + hb) * g.kx + hc];
+      hok |= (ok ? 1u : 0u) << u;
     }
   };
   auto store_h = [&](int a) {
     float *dst = ring + (a % (MG + 1)) * hplane;
 #pragma unroll
     for (int u = 0; u < RT_NH; ++u) {
+      asm volatile("" : "+v"(hreg[u]));  // keep the load's use here
       const int e = tid + u * MT;
-      if (e < hplane) dst[e] = hreg[u];
+      if (e < hplane) dst[e] = ((hok >> u) & 1u) ? hreg[u] : 0.f;
     }
   };
 
@@ -637,6 +644,7 @@ __device__ __forceinline__ void mfma_tile_rt(const float *__restrict__ in, const
 #pragma unroll
         for (int q = 0; q < MG; ++q) acc[q] += d[q];
       }
+      asm volatile("" ::: "memory");  // the stores stay after the matrix instructions
       if (more) store_plane(((zin + 1 - r_lo) & 1) ? tile1 : tile0);
       if (new_h) store_h(a_new);
       __syncthreads();
