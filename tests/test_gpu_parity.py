@@ -166,7 +166,7 @@ DH_CASES = [((6, 9, 11), (1, 2, 3)), ((16, 40, 40), (3, 2, 4)), ((20, 33), (2, 5
             # broadcast form (21- and 25-row PSF planes): scalar and 16-byte
             # staging, fewer X planes than PSF planes, ragged x tiles
             ((9, 37, 70), (4, 10, 10)), ((12, 40, 64), (15, 10, 10)), ((7, 150, 136), (3, 12, 12)),
-            ((5, 33, 257), (2, 10, 11))]
+            ((5, 33, 257), (2, 10, 11)), ((6, 30, 68), (2, 10, 11))]  # last: 16-byte X, scalar G
 
 
 @pytest.mark.parametrize("dtype", ["fp32", "fp64"])
