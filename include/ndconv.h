@@ -222,9 +222,9 @@ NDC_API int rl_iterate(int n, const int64_t *m, const int64_t *p, const void *Y,
                        void *stream);
 
 /* Batched form: many independent 3-D volumes, each with its own extents m,
- * half-widths p and PSF, in persistent launches that walk one tile list for
- * the whole batch.  Every volume keeps its own step size and acceptance
- * decisions (the rule of deconv_iterate); one trial slot of the whole batch
+ * half-widths p and PSF.  The deconvolution runs persistent launches that
+ * walk one tile list for the whole batch.  Every volume keeps its own step
+ * size and acceptance decisions (the rule of deconv_iterate); one trial slot of the whole batch
  * is captured once into a hipGraph and replayed per slot.  FP32 only; every
  * PSF needs 3 <= 2p_x+1 <= 33 and 2p_y+1 <= 33.
  *
@@ -234,19 +234,22 @@ NDC_API int rl_iterate(int n, const int64_t *m, const int64_t *p, const void *Y,
  *    volume first), use the hipGraph (0 or 1)}.  The plan owns small device
  *    tables; destroy it with ndc_batch_plan_destroy.
  *  ndc_batch_conv_full / ndc_batch_conv_adjoint: the two operators of every
- *    volume in one persistent launch; the pointer arguments are host arrays
- *    of count device pointers, read before the call returns (a small kernel
- *    receives them as launch arguments and writes the plan's device table).
+ *    volume, each volume's single-volume kernel (as conv_full_nd /
+ *    conv_adjoint_nd choose it) on one of the plan's 4 streams (each with a
+ *    hardware queue of its own), costliest volumes first, forked from and
+ *    joined back to `stream` with events; the pointer arguments are host
+ *    arrays of count device pointers, read before the call returns.
  *  ndc_batch_deconv: `iters` accepted steps on every volume, X[v] updated in
  *    place; ws holds ndc_batch_workspace_bytes(); stats is NULL or a host
  *    array of count nullable device pointers (each 4*(iters+1) doubles, as in
  *    deconv_iterate); info is NULL or a device array of 2*count ints
  *    (iters_done, status) per volume.  The same fixed schedule of
  *    2*iters + 30 trial slots as deconv_iterate, with the same stop codes.
- *  All three only enqueue work on `stream` and may be captured into a graph
- *  (inside a capture the step is enqueued kernel by kernel instead of as the
- *  plan's own graph).  Calls with one plan share its device tables, so they
- *  must be ordered on one stream; overlapping calls with one plan on
+ *  All three are ordered on `stream` (the operators' side streams wait for
+ *  it and it waits for them) and may be captured into a graph (inside a
+ *  capture the step is enqueued kernel by kernel instead of as the plan's own
+ *  graph).  Calls with one plan share its device tables, streams and events,
+ *  so they must be ordered on one stream; overlapping calls with one plan on
  *  different streams race.  Every output is checked against every input and
  *  every other output (NDC_EALIAS) and every pointer must be device memory
  *  (NDC_EINVAL) before anything is enqueued.  ndc_batch_plan_destroy waits

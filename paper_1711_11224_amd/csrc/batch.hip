@@ -273,6 +273,13 @@ struct ndc_batch_plan {
   hipStream_t cap = nullptr;
   hipGraphExec_t exec = nullptr;
   void *exec_ws = nullptr;
+  // the operators: each volume's compile-time tile on one of NOPS streams
+  // (default priority, a hardware queue each), costliest volumes first,
+  // forked from and joined back to the caller's stream with events
+  static constexpr int NOPS = 4;
+  hipStream_t ops[NOPS] = {};
+  hipEvent_t fork = nullptr, join[NOPS] = {};
+  std::vector<int> op_order, op_stream;  // launch order; stream of each launch
 };
 
 namespace {
@@ -440,6 +447,38 @@ int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dty
   if (!rc) rc = to_device(P->h_vols_conv.data(), sizeof(BVol) * count, (void **)&P->d_vols_conv);
   if (!rc) rc = to_device(P->off.data(), sizeof(BOff) * count, (void **)&P->d_off);
   if (!rc && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) rc = NDC_EDEVICE;
+  // The operator streams take a CU mask of every compute unit (no
+  // restriction), which gives each its own hardware queue.  Plain streams
+  // share HIP's small pool of hardware queues (4 by default): on MI355X two
+  // of the four landed on one queue each and ran in sequence, 11.2 ms per
+  // 64-volume forward against 9.0 ms on four queues of their own.
+  std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0xffffffffu);
+  if (cus % 32) mask.back() = (1u << (cus % 32)) - 1u;
+  for (int i = 0; !rc && i < ndc_batch_plan::NOPS; ++i)
+    if (hipExtStreamCreateWithCUMask(&P->ops[i], (uint32_t)mask.size(), mask.data()) != hipSuccess ||
+        hipEventCreateWithFlags(&P->join[i], hipEventDisableTiming) != hipSuccess)
+      rc = NDC_EDEVICE;
+  if (!rc && hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess) rc = NDC_EDEVICE;
+  P->op_order.resize(count);
+  for (int v = 0; v < count; ++v) P->op_order[v] = v;
+  {
+    auto cost = [&](int v) {  // taps x outputs of the forward
+      double c = 1.0;
+      for (int i = 0; i < 3; ++i) c *= (double)(2 * p[3 * v + i] + 1) * (double)(m[3 * v + i] + 2 * p[3 * v + i]);
+      return c;
+    };
+    std::stable_sort(P->op_order.begin(), P->op_order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    // each volume to the stream with the least work so far (longest first)
+    double load[ndc_batch_plan::NOPS] = {};
+    P->op_stream.resize(count);
+    for (int k = 0; k < count; ++k) {
+      int best = 0;
+      for (int i = 1; i < ndc_batch_plan::NOPS; ++i)
+        if (load[i] < load[best]) best = i;
+      P->op_stream[k] = best;
+      load[best] += cost(P->op_order[k]);
+    }
+  }
   if (rc) {
     ndc_batch_plan_destroy(P);
     return rc;
@@ -455,6 +494,11 @@ void ndc_batch_plan_destroy(ndc_batch_plan *P) {
   (void)hipDeviceSynchronize();
   if (P->exec) (void)hipGraphExecDestroy(P->exec);
   if (P->cap) (void)hipStreamDestroy(P->cap);
+  for (int i = 0; i < ndc_batch_plan::NOPS; ++i) {
+    if (P->ops[i]) (void)hipStreamDestroy(P->ops[i]);
+    if (P->join[i]) (void)hipEventDestroy(P->join[i]);
+  }
+  if (P->fork) (void)hipEventDestroy(P->fork);
   (void)hipFree(P->d_fwd);
   (void)hipFree(P->d_adj);
   (void)hipFree(P->d_vols);
@@ -553,16 +597,31 @@ int batch_conv(ndc_batch_plan *P, const void *const *in, const void *const *H, v
   for (int v = 0; v < P->count; ++v)
     if (!on_device(in[v]) || !on_device(H[v]) || !on_device(out[v])) return NDC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  // table fields: H, X (forward input / transpose output), R (the other one)
-  const void *const *xs = forward ? in : (const void *const *)out;
-  const void *const *rs = forward ? (const void *const *)out : in;
-  if (patch_table(P, P->d_vols_conv, false, nullptr, H, xs, rs, nullptr, nullptr, s) != hipSuccess)
-    return NDC_EDEVICE;
-  hipError_t e = forward ? launch_batch_conv(P->mg, P->d_vols_conv, P->d_fwd, (int)P->fwd.size(), BOP_FWD, nullptr,
-                                             P->grid, P->lds_fwd, s)
-                         : launch_batch_conv(P->mg, P->d_vols_conv, P->d_adj, (int)P->adj.size(), BOP_ADJ, nullptr,
-                                             P->grid, P->lds_adj, s);
-  return e == hipSuccess ? NDC_OK : NDC_EDEVICE;
+  // Each volume's own compile-time tile (the single-volume operator) on one
+  // of the plan's streams, costliest volumes first, each to the stream with
+  // the least work so far: the volumes' launches
+  // overlap, and each runs the tile with the fixed PSF width.  Measured on
+  // MI355X for 64 volumes of 32^3 .. 96x160x160 with PSFs 9..31: 17.4 ms per
+  // operator pair (9.1 forward, 8.1 transpose) on 4 streams against 24.6 ms
+  // for the persistent run-time-width tile (which the deconvolution keeps
+  // for its fused steps).
+  if (hipEventRecord(P->fork, s) != hipSuccess) return NDC_EDEVICE;
+  for (int i = 0; i < ndc_batch_plan::NOPS; ++i)
+    if (hipStreamWaitEvent(P->ops[i], P->fork, 0) != hipSuccess) return NDC_EDEVICE;
+  for (int k = 0; k < P->count; ++k) {
+    const int v = P->op_order[k];
+    const Geom g = forward ? forward_geom(&P->m[3 * v], &P->p[3 * v]) : adjoint_geom(&P->m[3 * v], &P->p[3 * v]);
+    const ConvPlan pl = plan_conv(g, NDC_F32, NDC_PREC_NATIVE);
+    Epi ep{};
+    ep.mode = EPI_STORE;
+    if (launch_conv(pl, g, NDC_F32, NDC_PREC_NATIVE, in[v], H[v], out[v], ep, P->ops[P->op_stream[k]]) !=
+        hipSuccess)
+      return NDC_EDEVICE;
+  }
+  for (int i = 0; i < ndc_batch_plan::NOPS; ++i)
+    if (hipEventRecord(P->join[i], P->ops[i]) != hipSuccess || hipStreamWaitEvent(s, P->join[i], 0) != hipSuccess)
+      return NDC_EDEVICE;
+  return NDC_OK;
 }
 
 }  // namespace
