@@ -13,9 +13,10 @@ process.
 
 Batches (tune): one plan per candidate tuning -- output planes per tile (2
 or 4), persistent work-groups per CU (1 or 2) and tile order (by volume,
-interleaved, costliest volume first) -- one forward plus one transpose
-launch each; the fastest is stored keyed by the batch's shapes, which
-plan_for() reads."""
+interleaved, costliest volume first) -- timed on two steps of the batched
+deconvolution, whose persistent launches the tuning shapes (the batched
+operators run each volume's own kernel and do not depend on it); the
+fastest is stored keyed by the batch's shapes, which plan_for() reads."""
 import hashlib
 import json
 import os
@@ -53,17 +54,19 @@ def save_entry(sig, entry, table=None):
     os.replace(tmp, path)
 
 
-def time_plan(plan, xs, hs, reps=2):
+def time_plan(plan, ys, hs, xs, reps=2, iters=2):
+    """Best of `reps` timings of `iters` batched deconvolution steps from the
+    same start (after one call that captures the plan's graph)."""
     s = torch.cuda.current_stream()
-    ys = plan.conv_full(xs, hs)
-    plan.conv_adjoint(ys, hs, xs=[torch.empty_like(x) for x in xs])
+    plan.deconv(ys, hs, [x.clone() for x in xs], iters)
     torch.cuda.synchronize()
     best = float("inf")
     for _ in range(reps):
+        x1 = [x.clone() for x in xs]
+        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
-        plan.conv_full(xs, hs, ys=ys)
-        plan.conv_adjoint(ys, hs)
+        plan.deconv(ys, hs, x1, iters)
         e1.record(s)
         torch.cuda.synchronize()
         best = min(best, e0.elapsed_time(e1))
@@ -74,12 +77,17 @@ def tune(shapes, psf_shapes, candidates=CANDIDATES, reps=2, table=None, seed=0):
     """Time every candidate on random data of the batch's shapes; store and
     return (best tuning, {tuning: ms})."""
     g = torch.Generator(device="cuda").manual_seed(seed)
-    xs = [torch.rand(s, device="cuda", generator=g) for s in shapes]
+    xt = [torch.rand(s, device="cuda", generator=g) for s in shapes]
     hs = [torch.rand(h, device="cuda", generator=g) for h in psf_shapes]
+    hs = [h / h.sum() for h in hs]
+    xs = [torch.rand(s, device="cuda", generator=g) for s in shapes]
     times = {}
+    ys = None
     for cand in candidates:
         plan = BatchPlan(shapes, psf_shapes, tuning=cand)
-        times[cand] = time_plan(plan, xs, hs, reps)
+        if ys is None:
+            ys = plan.conv_full(xt, hs)
+        times[cand] = time_plan(plan, ys, hs, xs, reps)
         plan.close()
     best = min(times, key=times.get)
     save_entry(signature(shapes, psf_shapes),
