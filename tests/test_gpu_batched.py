@@ -74,27 +74,25 @@ def mfma_path(psf):
 
 
 def test_batch_conv_equals_single_volume_bitwise(nd):
-    """Four output planes per tile, like the single-volume kernel: same sums
-    in the same order, so every output is bitwise equal (within 1e-6 where
-    the single-volume call takes the small-PSF kernel)."""
+    """The batched operators run each volume's single-volume kernel (on the
+    plan's side streams), so every output, small-PSF volumes included, is
+    bitwise equal to a single-volume call on the caller's stream; the
+    tuning (which shapes only the deconvolution's persistent launches) does
+    not change that."""
     say("case batch == single")
     rng = np.random.default_rng(11)
     xs, hs = small_batch(rng)
-    plan = nd.batched.BatchPlan([m for m, _ in SMALL], [k for _, k in SMALL], tuning=(4, 2, 1, 1))
     gx = [torch.from_numpy(x).cuda() for x in xs]
     gh = [torch.from_numpy(h).cuda() for h in hs]
-    ys = plan.conv_full(gx, gh)
-    gs = plan.conv_adjoint(ys, gh)
-    for v, (_, k) in enumerate(SMALL):
-        y1 = nd.conv_full_nd(gx[v], gh[v])
-        g1 = nd.conv_adjoint_nd(ys[v], gh[v])
-        if mfma_path(k):
-            assert torch.equal(ys[v], y1)
-            assert torch.equal(gs[v], g1)
-        else:
-            assert rel_l2(ys[v].cpu().numpy(), y1.cpu().numpy()) <= 1e-6
-            assert rel_l2(gs[v].cpu().numpy(), g1.cpu().numpy()) <= 1e-6
-    plan.close()
+    assert any(not mfma_path(k) for _, k in SMALL) and any(mfma_path(k) for _, k in SMALL)
+    for tuning in ((4, 2, 1, 1), (2, 1, 0, 0)):
+        plan = nd.batched.BatchPlan([m for m, _ in SMALL], [k for _, k in SMALL], tuning=tuning)
+        ys = plan.conv_full(gx, gh)
+        gs = plan.conv_adjoint(ys, gh)
+        for v in range(len(SMALL)):
+            assert torch.equal(ys[v], nd.conv_full_nd(gx[v], gh[v])), (tuning, v)
+            assert torch.equal(gs[v], nd.conv_adjoint_nd(ys[v], gh[v])), (tuning, v)
+        plan.close()
 
 
 def _deconv_inputs(rng, specs):
