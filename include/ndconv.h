@@ -223,16 +223,22 @@ NDC_API int rl_iterate(int n, const int64_t *m, const int64_t *p, const void *Y,
 
 /* Batched form: many independent 3-D volumes, each with its own extents m,
  * half-widths p and PSF.  The deconvolution runs persistent launches that
- * walk one tile list for the whole batch.  Every volume keeps its own step
- * size and acceptance decisions (the rule of deconv_iterate); one trial slot of the whole batch
- * is captured once into a hipGraph and replayed per slot.  FP32 only; every
+ * walk one tile list for the whole batch, or (tuning[0] = 0) each volume's
+ * own kernels on the plan's streams.  Every volume keeps its own step size
+ * and acceptance decisions (the rule of deconv_iterate); one trial slot of
+ * the whole batch is captured into a hipGraph (again when the workspace, or
+ * for tuning[0] = 0 any volume's address or lambda, differs from the last
+ * capture) and replayed per slot.  FP32 only; every
  * PSF needs 3 <= 2p_x+1 <= 33 and 2p_y+1 <= 33.
  *
  *  ndc_batch_plan_create: m and p are count x 3 host arrays (z, y, x);
- *    tuning is NULL or 4 ints {output planes per tile (2 or 4), work-groups
- *    per CU (1 or 2), tile order (0 by volume, 1 interleaved, 2 costliest
- *    volume first), use the hipGraph (0 or 1)}.  The plan owns small device
- *    tables; destroy it with ndc_batch_plan_destroy.
+ *    tuning is NULL or 4 ints {output planes per tile (2 or 4; 0: the
+ *    deconvolution's operators run each volume's own single-volume kernel on
+ *    the plan's streams instead of the persistent tile, and the next two
+ *    values are unused), work-groups per CU (1 or 2), tile order (0 by
+ *    volume, 1 interleaved, 2 costliest volume first), use the hipGraph (0
+ *    or 1)}.  The plan owns small device tables; destroy it with
+ *    ndc_batch_plan_destroy.
  *  ndc_batch_conv_full / ndc_batch_conv_adjoint: the two operators of every
  *    volume, each volume's single-volume kernel (as conv_full_nd /
  *    conv_adjoint_nd choose it) on one of the plan's 4 streams (each with a

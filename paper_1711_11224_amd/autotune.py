@@ -13,10 +13,11 @@ process.
 
 Batches (tune): one plan per candidate tuning -- output planes per tile (2
 or 4), persistent work-groups per CU (1 or 2) and tile order (by volume,
-interleaved, costliest volume first) -- timed on two steps of the batched
-deconvolution, whose persistent launches the tuning shapes (the batched
-operators run each volume's own kernel and do not depend on it); the
-fastest is stored keyed by the batch's shapes, which plan_for() reads."""
+interleaved, costliest volume first), or each volume's own kernels on the
+plan's streams -- timed on two steps of the batched deconvolution, the only
+call the tuning shapes (the batched operators run each volume's own kernel
+whatever it is); the fastest is stored keyed by the batch's shapes, which
+plan_for() reads."""
 import hashlib
 import json
 import os
@@ -27,7 +28,8 @@ from . import _native
 from .batched import BatchPlan
 
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_table.json")
-CANDIDATES = [(mg, wpc, order, 1) for mg in (4, 2) for wpc in (2, 1) for order in (0, 1, 2)]
+# the persistent tile's shapes, and (0, ...) the volumes' own kernels on the plan's streams
+CANDIDATES = [(mg, wpc, order, 1) for mg in (4, 2) for wpc in (2, 1) for order in (0, 1, 2)] + [(0, 1, 0, 1)]
 
 
 def signature(shapes, psf_shapes):

@@ -15,8 +15,9 @@ def _ptrs(tensors):
 
 class BatchPlan:
     """A plan for `shapes[v]` = (z, y, x) extents of X and `psf_shapes[v]` =
-    odd PSF extents.  tuning: None or (planes per tile 2|4, work-groups per
-    CU 1|2, order 0|1|2, use_graph 0|1)."""
+    odd PSF extents.  tuning: None or (planes per tile 2|4, or 0 for the
+    deconvolution on each volume's own kernels; work-groups per CU 1|2,
+    order 0|1|2, use_graph 0|1)."""
 
     def __init__(self, shapes, psf_shapes, tuning=None):
         if len(shapes) != len(psf_shapes) or not shapes:

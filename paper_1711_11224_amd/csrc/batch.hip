@@ -280,6 +280,13 @@ struct ndc_batch_plan {
   hipStream_t ops[NOPS] = {};
   hipEvent_t fork = nullptr, join[NOPS] = {};
   std::vector<int> op_order, op_stream;  // launch order; stream of each launch
+  // deconvolution on the volumes' own kernels (tuning[0] = 0): their launch
+  // plans, fixed at creation so that the partial-sum slot ranges stay valid
+  // whatever tile overrides are installed later
+  bool pervol = false;
+  std::vector<ConvPlan> pl_fwd, pl_adj;
+  std::vector<const void *> cur_ptrs, exec_ptrs;  // Y, H, X per volume: this call's; the step graph's
+  double cur_lambda = 0.0, exec_lambda = 0.0;
 };
 
 namespace {
@@ -337,13 +344,71 @@ int to_device(const void *h, size_t n, void **d) {
   return NDC_OK;
 }
 
+// One deconvolution operator of every volume on the volume's own kernel (the
+// single-volume epilogues: RESID for the first and trial residuals, UPDATE
+// for the transpose with the projected step), on the plan's streams, forked
+// from and joined back to s.  Each volume's partial sums go to its own slot
+// range (one pair per work-group), which the per-volume control kernels
+// read; the phase word gates the step operators as in the persistent tile.
+hipError_t launch_vols(ndc_batch_plan *P, char *ws, int op, double *part, hipStream_t s) {
+  hipError_t e = hipEventRecord(P->fork, s);
+  for (int i = 0; e == hipSuccess && i < ndc_batch_plan::NOPS; ++i) e = hipStreamWaitEvent(P->ops[i], P->fork, 0);
+  if (e != hipSuccess) return e;
+  const bool fwd = op != BOP_STEP_ADJ;
+  for (int k = 0; k < P->count; ++k) {
+    const int v = P->op_order[k];
+    const BVol &b = P->h_vols[v];
+    const BOff &f = P->off[v];
+    DState *st = (DState *)(ws + P->off_state) + v;
+    const void *H = P->cur_ptrs[3 * v + 1];
+    float *X = (float *)P->cur_ptrs[3 * v + 2];
+    Epi ep{};
+    ep.part = part + 2 * (int64_t)(fwd ? b.fwd_lo : b.adj_lo);
+    const void *in;
+    void *out;
+    if (op == BOP_STEP_ADJ) {
+      in = ws + f.r;
+      out = ws + f.xt;
+      ep.mode = EPI_UPDATE;
+      ep.X = X;
+      ep.G = ws + f.g;
+      ep.lambda = P->cur_lambda;
+      ep.delta = &st->delta;
+      ep.phase = &st->phase;
+      ep.phase_mask = 1 << PH_NEW;
+    } else {
+      in = op == BOP_INIT ? (const void *)X : (const void *)(ws + f.xt);
+      out = ws + (op == BOP_INIT ? f.r : f.rt);
+      ep.mode = EPI_RESID;
+      ep.Y = P->cur_ptrs[3 * v];
+      if (op == BOP_STEP_FWD) {
+        ep.phase = &st->phase;
+        ep.phase_mask = (1 << PH_NEW) | (1 << PH_RETRY);
+      }
+    }
+    const Geom g = fwd ? forward_geom(&P->m[3 * v], &P->p[3 * v]) : adjoint_geom(&P->m[3 * v], &P->p[3 * v]);
+    e = launch_conv(fwd ? P->pl_fwd[v] : P->pl_adj[v], g, NDC_F32, NDC_PREC_NATIVE, in, H, out, ep,
+                    P->ops[P->op_stream[k]]);
+    if (e != hipSuccess) return e;
+  }
+  for (int i = 0; e == hipSuccess && i < ndc_batch_plan::NOPS; ++i) {
+    e = hipEventRecord(P->join[i], P->ops[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, P->join[i], 0);
+  }
+  return e;
+}
+
 hipError_t launch_step(ndc_batch_plan *P, char *ws, hipStream_t s) {
   double *pf = (double *)(ws + P->off_pf), *pa = (double *)(ws + P->off_pa), *pe = (double *)(ws + P->off_pe);
   hipError_t e;
-  e = launch_batch_conv(P->mg, P->d_vols, P->d_adj, (int)P->adj.size(), BOP_STEP_ADJ, pa, P->grid, P->lds_adj, s);
+  e = P->pervol ? launch_vols(P, ws, BOP_STEP_ADJ, pa, s)
+                : launch_batch_conv(P->mg, P->d_vols, P->d_adj, (int)P->adj.size(), BOP_STEP_ADJ, pa, P->grid,
+                                    P->lds_adj, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(b_update_kernel, dim3(P->count * EB), dim3(BT), 0, s, (const BVol *)P->d_vols, pe);
-  e = launch_batch_conv(P->mg, P->d_vols, P->d_fwd, (int)P->fwd.size(), BOP_STEP_FWD, pf, P->grid, P->lds_fwd, s);
+  e = P->pervol ? launch_vols(P, ws, BOP_STEP_FWD, pf, s)
+                : launch_batch_conv(P->mg, P->d_vols, P->d_fwd, (int)P->fwd.size(), BOP_STEP_FWD, pf, P->grid,
+                                    P->lds_fwd, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(b_decide_kernel, dim3(P->count), dim3(BT), 0, s, (const BVol *)P->d_vols, (const double *)pf,
                      (const double *)pa, (const double *)pe);
@@ -376,11 +441,13 @@ int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dty
     wpc = tuning[1];
     order = tuning[2];
     graph = tuning[3];
-    if ((mg != 2 && mg != 4) || wpc < 1 || wpc > 2 || order < 0 || order > 2 || graph < 0 || graph > 1)
+    if ((mg != 0 && mg != 2 && mg != 4) || wpc < 1 || wpc > 2 || order < 0 || order > 2 || graph < 0 || graph > 1)
       return NDC_EINVAL;
   }
   ndc_batch_plan *P = new ndc_batch_plan();
   P->count = count;
+  P->pervol = mg == 0;
+  if (P->pervol) mg = 4;  // the tile lists still exist (unused by the steps)
   P->mg = mg;
   P->wg_per_cu = wpc;
   P->order = order;
@@ -397,14 +464,36 @@ int ndc_batch_plan_create(int count, const int64_t *m, const int64_t *p, int dty
     return NDC_EDEVICE;
   }
   P->grid = cus * wpc;
+  // per-volume kernels: their plans, and partial-sum slot ranges of one pair
+  // per work-group in place of the tile ranges
+  size_t nslot_fwd = P->fwd.size(), nslot_adj = P->adj.size();
+  if (P->pervol) {
+    int64_t sf = 0, sa = 0;
+    for (int v = 0; v < count; ++v) {
+      P->pl_fwd.push_back(plan_conv(forward_geom(&m[3 * v], &p[3 * v]), NDC_F32, NDC_PREC_NATIVE));
+      P->pl_adj.push_back(plan_conv(adjoint_geom(&m[3 * v], &p[3 * v]), NDC_F32, NDC_PREC_NATIVE));
+      flo[v] = (int)sf;
+      sf += P->pl_fwd[v].nblocks;
+      fhi[v] = (int)sf;
+      alo[v] = (int)sa;
+      sa += P->pl_adj[v].nblocks;
+      ahi[v] = (int)sa;
+      if (sf >= (int64_t)1 << 30 || sa >= (int64_t)1 << 30) {
+        delete P;
+        return NDC_EUNSUPPORTED;
+      }
+    }
+    nslot_fwd = (size_t)sf;
+    nslot_adj = (size_t)sa;
+  }
   // workspace layout and the volume tables
   size_t o = 0;
   P->off_state = o;
   o += al256(sizeof(DState) * count);
   P->off_pf = o;
-  o += al256(sizeof(double) * 2 * P->fwd.size());
+  o += al256(sizeof(double) * 2 * nslot_fwd);
   P->off_pa = o;
-  o += al256(sizeof(double) * 2 * P->adj.size());
+  o += al256(sizeof(double) * 2 * nslot_adj);
   P->off_pe = o;
   o += al256(sizeof(double) * 2 * (size_t)count * EB);
   P->h_vols.resize(count);
@@ -666,10 +755,18 @@ int ndc_batch_deconv(ndc_batch_plan *P, const void *const *Y, const void *const 
   if (patch_table(P, P->d_vols, true, w, (const void *const *)Y, (const void *const *)H, (const void *const *)X,
                   (const void *const *)stats, info, s) != hipSuccess)
     return NDC_EDEVICE;
+  P->cur_ptrs.resize(3 * (size_t)P->count);
+  for (int v = 0; v < P->count; ++v) {
+    P->cur_ptrs[3 * v] = Y[v];
+    P->cur_ptrs[3 * v + 1] = H[v];
+    P->cur_ptrs[3 * v + 2] = X[v];
+  }
+  P->cur_lambda = lambda;
   hipLaunchKernelGGL(b_init_kernel, dim3(P->count), dim3(BT), 0, s, (const BVol *)P->d_vols, lambda, iters, 30);
   hipLaunchKernelGGL(b_sumsq_kernel, dim3(P->count * EB), dim3(BT), 0, s, (const BVol *)P->d_vols, pe);
-  if (launch_batch_conv(P->mg, P->d_vols, P->d_fwd, (int)P->fwd.size(), BOP_INIT, pf, P->grid, P->lds_fwd, s) !=
-      hipSuccess)
+  if ((P->pervol ? launch_vols(P, w, BOP_INIT, pf, s)
+                 : launch_batch_conv(P->mg, P->d_vols, P->d_fwd, (int)P->fwd.size(), BOP_INIT, pf, P->grid,
+                                     P->lds_fwd, s)) != hipSuccess)
     return NDC_EDEVICE;
   hipLaunchKernelGGL(b_f0_kernel, dim3(P->count), dim3(BT), 0, s, (const BVol *)P->d_vols, (const double *)pf,
                      (const double *)pe);
@@ -680,11 +777,18 @@ int ndc_batch_deconv(ndc_batch_plan *P, const void *const *Y, const void *const 
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess) return NDC_EDEVICE;
   const bool graph = P->use_graph && cs == hipStreamCaptureStatusNone;
-  if (graph && P->exec_ws != ws) {  // capture one slot against this workspace
+  // The persistent step reads every address from the device table, so its
+  // graph depends on the workspace alone; the per-volume kernels take the
+  // volumes' addresses and lambda as launch arguments, so their graph is
+  // captured again whenever one of those changes.
+  const bool stale = P->exec_ws != ws ||
+                     (P->pervol && (P->exec_ptrs != P->cur_ptrs || !(P->exec_lambda == lambda)));
+  if (graph && stale) {  // capture one slot against this workspace
     if (P->exec) {
       (void)hipGraphExecDestroy(P->exec);
       P->exec = nullptr;
     }
+    P->exec_ws = nullptr;  // no valid graph until the capture below succeeds
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return NDC_EDEVICE;
     const hipError_t le = launch_step(P, w, P->cap);
@@ -697,6 +801,8 @@ int ndc_batch_deconv(ndc_batch_plan *P, const void *const *Y, const void *const 
       return NDC_EDEVICE;
     }
     P->exec_ws = ws;
+    P->exec_ptrs = P->cur_ptrs;
+    P->exec_lambda = lambda;
   }
   // the same fixed schedule as deconv_iterate: 2*iters + 30 trial slots
   const int slots = iters > 0 ? 2 * iters + 30 : 0;

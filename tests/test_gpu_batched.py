@@ -107,12 +107,17 @@ def _deconv_inputs(rng, specs):
     return ys, hs, x0s
 
 
-def test_batch_deconv_vs_oracle_and_single(nd):
-    say("case batch deconv")
+# the persistent tile, and each volume's own kernels on the plan's streams
+STEP_FORMS = [(4, 2, 0), (0, 1, 0)]
+
+
+@pytest.mark.parametrize("form", STEP_FORMS)
+def test_batch_deconv_vs_oracle_and_single(nd, form):
+    say("case batch deconv", form)
     rng = np.random.default_rng(12)
     specs = SMALL[:4]
     ys, hs, x0s = _deconv_inputs(rng, specs)
-    plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=(4, 2, 0, 1))
+    plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=form + (1,))
     gy = [torch.from_numpy(a).cuda() for a in ys]
     gh = [torch.from_numpy(a).cuda() for a in hs]
     gx = [torch.from_numpy(a).cuda() for a in x0s]
@@ -128,7 +133,7 @@ def test_batch_deconv_vs_oracle_and_single(nd):
         # X bitwise equal to the single-volume path (every output is the same sum
         # in the same order); f is summed over that path's own tile partition
         x1, st1, inf1 = nd.deconv_iterate(gy[v], gh[v], torch.from_numpy(x0s[v]).cuda(), 8, lam=0.1)
-        if mfma_path(specs[v][1]):
+        if mfma_path(specs[v][1]) or form[0] == 0:
             assert torch.equal(x1, xs[v])
             np.testing.assert_allclose(st1.cpu().numpy(), stats[v].cpu().numpy(), rtol=1e-12, equal_nan=True)
         else:
@@ -136,18 +141,19 @@ def test_batch_deconv_vs_oracle_and_single(nd):
     plan.close()
 
 
-def test_batch_graph_replays_equal_eager(nd):
+@pytest.mark.parametrize("form", STEP_FORMS)
+def test_batch_graph_replays_equal_eager(nd, form):
     """The hipGraph-captured step replayed many times, with eager work and
     synchronisations between calls, gives bitwise the same result as the
     same kernels launched one by one."""
-    say("case batch graph vs eager")
+    say("case batch graph vs eager", form)
     rng = np.random.default_rng(13)
     specs = SMALL[:3]
     for trial in range(2):
         ys, hs, x0s = _deconv_inputs(rng, specs)
         out = {}
         for graph in (1, 0):
-            plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=(4, 2, 0, graph))
+            plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=form + (graph,))
             gx = [torch.from_numpy(a).cuda() for a in x0s]
             xs, stats, info = plan.deconv([torch.from_numpy(a).cuda() for a in ys],
                                           [torch.from_numpy(a).cuda() for a in hs], gx, 6)
@@ -162,15 +168,16 @@ def test_batch_graph_replays_equal_eager(nd):
         assert torch.equal(out[1][2], out[0][2])
 
 
-def test_batch_calls_capture_into_a_graph(nd):
+@pytest.mark.parametrize("form", STEP_FORMS)
+def test_batch_calls_capture_into_a_graph(nd, form):
     """ndc_batch_deconv and the batched operators enqueue work only, so a
     caller can capture them; replays from the same X^0 (restored eagerly in
     between) equal eager calls bitwise."""
-    say("case batch capture")
+    say("case batch capture", form)
     rng = np.random.default_rng(14)
     specs = SMALL[:3]
     ys, hs, x0s = _deconv_inputs(rng, specs)
-    plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=(4, 2, 0, 1))
+    plan = nd.batched.BatchPlan([m for m, _ in specs], [k for _, k in specs], tuning=form + (1,))
     gy = [torch.from_numpy(a).cuda() for a in ys]
     gh = [torch.from_numpy(a).cuda() for a in hs]
     x0 = [torch.from_numpy(a).cuda() for a in x0s]
@@ -205,6 +212,34 @@ def test_batch_calls_capture_into_a_graph(nd):
     del g
     torch.cuda.synchronize()
     plan.close()
+
+
+def test_batch_step_graph_follows_new_arrays(nd):
+    """With the volumes' own kernels the step graph carries the call's
+    addresses and lambda: one plan called on two sets of arrays and two
+    lambdas, alternately, matches a plan without the graph on every call."""
+    say("case batch graph recapture")
+    rng = np.random.default_rng(15)
+    specs = SMALL[:3]
+    shapes, psfs = [m for m, _ in specs], [k for _, k in specs]
+    sets = []
+    for _ in range(2):
+        ys, hs, x0s = _deconv_inputs(rng, specs)
+        sets.append(([torch.from_numpy(a).cuda() for a in ys], [torch.from_numpy(a).cuda() for a in hs], x0s))
+    plan = nd.batched.BatchPlan(shapes, psfs, tuning=(0, 1, 0, 1))
+    ref = nd.batched.BatchPlan(shapes, psfs, tuning=(0, 1, 0, 0))
+    for call, (si, lam) in enumerate([(0, 0.0), (1, 0.0), (0, 0.0), (0, 0.05), (1, 0.05)]):
+        gy, gh, x0s = sets[si]
+        xa, sa, ia = plan.deconv(gy, gh, [torch.from_numpy(a).cuda() for a in x0s], 4, lam=lam)
+        xb, sb, ib = ref.deconv(gy, gh, [torch.from_numpy(a).cuda() for a in x0s], 4, lam=lam)
+        torch.cuda.synchronize()
+        assert torch.equal(ia, ib), call
+        for a, b in zip(xa, xb):
+            assert torch.equal(a, b), call
+        for a, b in zip(sa, sb):
+            assert same(a, b), call
+    plan.close()
+    ref.close()
 
 
 def test_batched_workload_64_volumes(nd):
