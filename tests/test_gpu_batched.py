@@ -242,13 +242,15 @@ def test_batch_step_graph_follows_new_arrays(nd):
     ref.close()
 
 
-def test_batched_workload_64_volumes(nd):
+@pytest.mark.parametrize("form", STEP_FORMS)
+def test_batched_workload_64_volumes(nd, form):
     """The batched workload: 64 volumes of 32^3 .. 96x160x160 with their own
     Gaussian PSFs (odd extents 9..31 per axis), 50 steps in one plan with
-    the hipGraph.  Every volume runs all steps with f strictly decreasing and
-    X >= 0; three volumes are rerun alone and must match bitwise."""
+    the hipGraph, in both step forms (the bench's tuning takes the volumes'
+    own kernels).  Every volume runs all steps with f strictly decreasing
+    and X >= 0; three volumes are rerun alone and must match bitwise."""
     cfgs = synth.batched_configs(64)
-    say("case c4 batched 64")
+    say("case c4 batched 64", form)
     ys, hs, x0s = [], [], []
     for c in cfgs:
         x = synth.make_objects(c)
@@ -258,7 +260,8 @@ def test_batched_workload_64_volumes(nd):
         ys.append(torch.from_numpy(y).cuda())
         hs.append(torch.from_numpy(h).cuda())
         x0s.append(synth.flat_start(y, h, c.shape).astype(np.float32))
-    plan = nd.batched.BatchPlan([c.shape for c in cfgs], [c.psf_shape for c in cfgs], tuning=(4, 2, 2, 1))
+    plan = nd.batched.BatchPlan([c.shape for c in cfgs], [c.psf_shape for c in cfgs],
+                                tuning=(4, 2, 2, 1) if form[0] else (0, 1, 0, 1))
     xs = [torch.from_numpy(a).cuda() for a in x0s]
     xs, stats, info = plan.deconv(ys, hs, xs, 50)
     info = info.cpu().numpy()
