@@ -75,9 +75,16 @@ def time_plan(plan, ys, hs, xs, reps=2, iters=2):
     return best
 
 
-def tune(shapes, psf_shapes, candidates=CANDIDATES, reps=2, table=None, seed=0):
+def tune(shapes, psf_shapes, candidates=CANDIDATES, reps=2, table=None, seed=0, forms=True):
     """Time every candidate on random data of the batch's shapes; store and
-    return (best tuning, {tuning: ms})."""
+    return (best tuning, {tuning: ms}).  With forms=True each distinct
+    volume problem first gets its kernel forms tuned and stored (tune_conv):
+    the batched operators, and the deconvolution on the volumes' own
+    kernels, run the form installed for each volume."""
+    if forms:
+        for shape, psf in sorted({(tuple(int(v) for v in a), tuple(int(v) for v in b))
+                                  for a, b in zip(shapes, psf_shapes)}):
+            tune_conv(shape, psf, table=table, seed=seed)
     g = torch.Generator(device="cuda").manual_seed(seed)
     xt = [torch.rand(s, device="cuda", generator=g) for s in shapes]
     hs = [torch.rand(h, device="cuda", generator=g) for h in psf_shapes]
@@ -96,6 +103,22 @@ def tune(shapes, psf_shapes, candidates=CANDIDATES, reps=2, table=None, seed=0):
                {"tuning": list(best), "ms": {",".join(map(str, k)): round(v, 4) for k, v in times.items()}},
                table)
     return best, times
+
+
+def install_batch_forms(shapes, psf_shapes, table=None):
+    """Install the stored kernel forms of a batch's volumes (entries that
+    tune_conv wrote); returns how many operator choices were installed."""
+    entries = load_table(table)
+    count = 0
+    for shape, psf in {(tuple(int(v) for v in a), tuple(int(v) for v in b)) for a, b in zip(shapes, psf_shapes)}:
+        e = entries.get(conv_signature(shape, psf, "fp32", torch.float32))
+        for op in OPS if e else ():
+            try:
+                set_form(shape, psf, op, e[op]["form"][0], e[op]["form"][1])
+                count += 1
+            except _native.NdcError:
+                pass
+    return count
 
 
 def best_tuning(shapes, psf_shapes, table=None):

@@ -98,8 +98,11 @@ class BatchPlan:
 
 def plan_for(shapes, psf_shapes, tuning="auto", table=None):
     """A BatchPlan whose tuning comes from the autotuner's table (tuning the
-    batch first if the table has no entry for it) or is given explicitly."""
+    batch first if the table has no entry for it) or is given explicitly;
+    with "auto" the volumes' stored kernel forms are installed first, so the
+    plan's per-volume kernels are the tuned ones."""
     if tuning == "auto":
-        from .autotune import best_tuning
+        from .autotune import best_tuning, install_batch_forms
         tuning = best_tuning(shapes, psf_shapes, table=table)
+        install_batch_forms(shapes, psf_shapes, table=table)
     return BatchPlan(shapes, psf_shapes, tuning=tuning)

@@ -303,17 +303,38 @@ def test_batched_workload_64_volumes_operators_sampled(nd):
 
 
 def test_autotuner_table(nd, tmp_path):
+    """The batch tuner stores the batch's tuning and each volume's kernel
+    forms; plan_for installs those forms, and the batched operators then
+    run them (bitwise equal to single-volume calls with the same forms)."""
     from paper_1711_11224_amd import autotune
     say("case autotune")
     specs = SMALL[:3]
     shapes, psfs = [m for m, _ in specs], [k for _, k in specs]
     table = str(tmp_path / "table.json")
-    best, times = autotune.tune(shapes, psfs, candidates=[(4, 2, 0, 1), (2, 2, 1, 1), (4, 1, 2, 1)], table=table)
-    assert best in times and times[best] == min(times.values())
-    assert autotune.best_tuning(shapes, psfs, table=table) == best
-    plan = nd.batched.plan_for(shapes, psfs, table=table)
-    assert plan.tuning == best
-    plan.close()
+    try:
+        best, times = autotune.tune(shapes, psfs, candidates=[(4, 2, 0, 1), (2, 2, 1, 1), (4, 1, 2, 1), (0, 1, 0, 1)],
+                                    table=table)
+        assert best in times and times[best] == min(times.values())
+        assert autotune.best_tuning(shapes, psfs, table=table) == best
+        entries = autotune.load_table(table)
+        stored = {}
+        for m, k in specs:
+            e = entries[autotune.conv_signature(m, k, "fp32", torch.float32)]
+            stored[(m, k)] = tuple(tuple(e[op]["form"]) for op in autotune.OPS)
+        nd.lib.ndc_tile_override_clear()
+        plan = nd.batched.plan_for(shapes, psfs, table=table)
+        assert plan.tuning == best
+        for m, k in specs:
+            assert tuple(autotune.current_form(m, k, op) for op in autotune.OPS) == stored[(m, k)]
+        rng = np.random.default_rng(16)
+        gx = [torch.from_numpy(rng.random(m).astype(np.float32)).cuda() for m, _ in specs]
+        gh = [torch.from_numpy(rng.standard_normal(k).astype(np.float32)).cuda() for _, k in specs]
+        ys = plan.conv_full(gx, gh)
+        for v in range(len(specs)):
+            assert torch.equal(ys[v], nd.conv_full_nd(gx[v], gh[v]))
+        plan.close()
+    finally:
+        nd.lib.ndc_tile_override_clear()  # leave no forms installed for later tests
 
 
 @pytest.mark.parametrize("tuning", [(4, 2, 2, 1), (2, 1, 0, 0)])
