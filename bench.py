@@ -275,13 +275,15 @@ def bench_joint_refinement(nd, torch, steps=20, sigma_steps=60):
             "true_sigmas": list(cfg.sigmas), "guess_sigmas": list(guess)}
 
 
-def bench_batched(nd, torch, steps=5, table=None):
+def bench_batched(nd, torch, steps=None, table=None):
     """Batched workload: 64 volumes of 32^3 .. 96x160x160, each with its own
     Gaussian PSF of odd extents 9..31, FP32, one hipGraph-captured step per
-    iteration, tuning from the autotuner's table."""
+    iteration, tuning from the autotuner's table; one call runs the
+    workload's own iteration count (50) unless `steps` is given."""
     import synth
     from paper_1711_11224_amd.batched import plan_for
     cfgs = synth.batched_configs(64)
+    steps = steps or cfgs[0].iters
     shapes, psfs = [c.shape for c in cfgs], [c.psf_shape for c in cfgs]
     t = time.time()
     plan = plan_for(shapes, psfs, tuning="auto", table=table)
